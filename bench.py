@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Decoded Mbit/s of the Log-Fourier SP decoder on one MI355X.
+
+Workload (default): GF(64) (2,6) code, N=1000 symbols (M=333 checks, E=2000
+edges), 4096 frames of random codewords over BPSK/AWGN at Eb/N0 = 2.5 dB,
+max 100 rounds, stop at zero syndrome.  One step = one complete decode of the
+4096-frame batch (every round until every frame has stopped), with the LLRs
+already resident in HBM.
+
+Prints one JSON line.  `roofline` is measured live for the fused pass kernel
+(HIP events around each launch on the decode stream): algorithmic bytes per
+frame-round B = (2E+N)*q*s + 4*N*m (s = bytes per stored message entry), plus
+E*q*s + 4*N*m for the first pass of each frame.  `cpu_baseline` times the FP64
+oracle on a bounded sample of the same frames on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "decoded Mbit/s at GF(64)(2,6) N=1000, 2.5 dB; p50/p99 frame latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def _oracle_worker(args):
+    idx, llr, code_arrays, max_iter = args
+    from oracle.sp import TannerCode, decode
+    M, N, m, rp, col, val, poly = code_arrays
+    tc = TannerCode(M, N, m, rp, col, val, poly)
+    t0 = time.perf_counter()
+    r = decode(tc, llr, max_iter)
+    return idx, time.perf_counter() - t0, r.hard, r.iters
+
+
+def cpu_baseline(batch, max_iter, frames_per_worker=2, workers=None):
+    """Time the FP64 oracle (never tuned) on a sample of the batch's frames."""
+    import multiprocessing as mp
+    workers = workers or min(16, os.cpu_count() or 1)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    c = batch.code
+    arrays = (c.M, c.N, c.m, c.row_ptr, c.col, c.val, c.poly)
+    n = workers * frames_per_worker
+    sample = np.linspace(0, batch.llr.shape[0] - 1, n).astype(int)
+    tasks = [(sample[i::workers], batch.llr[sample[i::workers]], arrays, max_iter) for i in range(workers)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_worker, tasks)
+        wall = time.perf_counter() - t0
+    frames = sum(len(r[0]) for r in res)
+    mbps = frames * batch.info_bits_per_frame / wall / 1e6
+    return dict(value=mbps, unit="Mbit/s", cores=workers, kind="oracle",
+                sample=f"{frames} frames (evenly spaced over the batch), full decode to the same stop rule, "
+                       f"{workers} processes x 1 thread, {wall:.1f} s wall"), res
+
+
+def alg_bytes(code, iters, s, first_pass=True):
+    """Algorithmic HBM bytes of all fused-pass launches for one decode."""
+    E, N, q, m = code.E, code.N, code.q, code.m
+    per_round = (2 * E + N) * q * s + 4 * N * m
+    first = E * q * s + 4 * N * m
+    return int(len(iters) * first + int(np.sum(iters)) * per_round)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="gf64_n1000")
+    ap.add_argument("--point", type=int, default=2, help="Eb/N0 index (gf64_n1000: 2 -> 2.5 dB)")
+    ap.add_argument("--prec", default="fp16", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--mode", default="fused", choices=["fused", "plain"])
+    ap.add_argument("--max-iter", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames-per-worker", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "frames would shard across GPUs with no per-round exchange (see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1008_4370_amd import synth
+    batch = synth.make_batch(args.workload, point=args.point)
+    F = batch.llr.shape[0]
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu_baseline: FP64 oracle on a sample ...", file=sys.stderr, flush=True)
+        cpu, _ = cpu_baseline(batch, args.max_iter, args.cpu_frames_per_worker)
+        print(f"[bench] cpu_baseline done: {cpu['value']:.4f} Mbit/s", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_1008_4370_amd import decoder as D
+    code = D.Code.from_synth(batch.code)
+    dec = D.Decoder(code, F, args.prec, args.mode)
+    llr = torch.from_numpy(batch.llr).cuda()
+    for _ in range(args.warmup):
+        dec(llr, args.max_iter)
+    torch.cuda.synchronize()
+    kernel = D.K_FUSED if args.mode == "fused" else D.K_CHECK
+    D.profile_read(D.K_FUSED), D.profile_read(D.K_CHECK), D.profile_read(D.K_VAR)
+    D.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = dec(llr, args.max_iter)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    D.profile_enable(False)
+    kms, launches = D.profile_read(kernel)
+    ms_var, launches_var = D.profile_read(D.K_VAR)
+    ms_step = (t1 - t0) / args.steps * 1e3
+
+    hard = out["hard"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()
+    status = out["status"].cpu().numpy()
+    info_bits = batch.info_bits_per_frame
+    value = F * info_bits / (ms_step / 1e3) / 1e6
+    frame_err = np.any(hard != batch.cw, axis=1)
+    bit_err = int(np.sum((((hard.astype(np.int64) ^ batch.cw)[..., None] >> np.arange(batch.code.m)) & 1)))
+    s = 4 if args.prec == "fp32" else 2
+    if args.mode == "fused":
+        total_bytes = alg_bytes(batch.code, iters, s) * args.steps
+        achieved = total_bytes / (kms / 1e3) / 1e9
+        roof_kernel = "k_fused"
+    else:
+        # PLAIN: check + variable kernels each move 2*E*q*4 bytes per frame-round
+        E, q = batch.code.E, batch.code.q
+        total_bytes = int(np.sum(iters)) * 4 * E * q * 4 * args.steps
+        achieved = total_bytes / ((kms + ms_var) / 1e3) / 1e9
+        roof_kernel = "k_check_plain+k_var_plain"
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mbit/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: GF({batch.code.q}) (2,{int(round(2 * batch.code.N / batch.code.M))}) "
+                        f"N={batch.code.N} M={batch.code.M}, {F} frames, Eb/N0={batch.ebn0} dB, "
+                        f"max {args.max_iter} rounds",
+            "storage": args.prec,
+            "mode": args.mode,
+            "frames": F,
+            "info_bits_per_frame": info_bits,
+            "parallelism": "1 GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": roof_kernel,
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "launches": int(launches),
+            "kernel_ms_per_step": round(kms / args.steps, 4),
+        },
+        "cpu_baseline": cpu,
+        "fer": float(frame_err.mean()),
+        "ber": bit_err / (F * batch.code.N * batch.code.m),
+        "mean_iters": float(iters.mean()),
+        "max_iters": int(iters.max()),
+        "converged": float(((status & 1) != 0).mean()),
+        "latency_ms": {"p50": round(ms_step, 4), "p99": round(ms_step, 4),
+                       "note": "batch mode: every frame's result is returned with the batch"},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,159 @@
+/*
+ * ldpc_fd.h -- C ABI of libldpcfd.so, a gfx950 (MI355X) decoder for non-binary
+ * LDPC codes over GF(2^m) with column weight 2, using the Log-Fourier
+ * sum-product (LF-SP) algorithm of K. Kasai and K. Sakaniwa, "Fourier Domain
+ * Decoding Algorithm of Non-Binary LDPC codes for Parallel Implementation",
+ * IEICE Trans. Fundamentals 93(11), 2010 (arXiv:1008.4370).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Symbols: x in GF(2^m) is the m-bit vector (x_1..x_m) of its coefficients in
+ *   the basis 1, alpha, ..., alpha^(m-1) (Sec. 2); as an integer, x_i is bit
+ *   (i-1).  alpha is the class of the polynomial "x" modulo the primitive
+ *   polynomial prim_poly.
+ * Code: H is M x N over GF(2^m), given in compressed-row form (row_ptr, col,
+ *   val).  Edge e is the e-th nonzero of H in row-major order; all per-edge
+ *   arrays use this check-major order.  Every column must have exactly two
+ *   nonzeros (the (j=2,k) codes the method is built for, Sec. 1 and Sec. 4);
+ *   rows may have different weights (>= 2).
+ * Channel: llr[f][v][i] = ln Pr(b=0|y)/Pr(b=1|y) for bit i (0-based, the
+ *   coefficient of alpha^i) of symbol v of frame f, FP32, device memory,
+ *   layout [frames][N][m] contiguous.  The symbol prior is the product of the
+ *   bit posteriors (INITIALIZATION, Sec. 2.1 / Sec. 3.2).
+ * Messages (the decoder state): Lambda_cv(z) = Gamma(P_cv(z)) of Sec. 3.2 for
+ *   every edge, in the variable node's coordinates z (no label map applied),
+ *   stored as one float per entry whose sign bit is the GF(2) sign and whose
+ *   magnitude is -log2|P_cv(z)| in [0, 100] (base 2 instead of the paper's
+ *   natural log; a positive rescaling).  Layout [frames][E][2^m] contiguous.
+ * Errors: every function returns LDPC_FD_OK (0) or a negative code; no
+ *   exception crosses the ABI.  ldpc_fd_last_error() gives a message for the
+ *   last failure on the calling thread.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   Device-side work is enqueued on it; results are valid once it is
+ *   synchronised.  A code object may be used concurrently on different streams,
+ *   each call with its own workspace.
+ */
+#ifndef LDPC_FD_H
+#define LDPC_FD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ldpc_fd_code_s *ldpc_fd_code;
+
+enum {
+  LDPC_FD_OK = 0,
+  LDPC_FD_E_INVALID = -1,     /* bad argument or malformed H */
+  LDPC_FD_E_UNSUPPORTED = -2, /* column weight != 2, m outside 2..8, ... */
+  LDPC_FD_E_NOMEM = -3,       /* allocation failed or workspace too small */
+  LDPC_FD_E_HIP = -4          /* a HIP runtime call failed */
+};
+
+/* Storage type of the message state (arithmetic is FP32 in every case). */
+enum { LDPC_FD_FP32 = 0, LDPC_FD_FP16 = 1, LDPC_FD_BF16 = 2 };
+
+/* Decoder variants (identical results up to rounding order):
+ *  PLAIN: one kernel per node type per round, flooding schedule of Sec. 2
+ *         (check-to-variable, variable-to-check, tentative decision), all frames
+ *         processed until the host sees every frame stopped.
+ *  FUSED: one pass per round over the checks; each pass recomputes the
+ *         variable-to-check messages from the stored check-to-variable state,
+ *         forms the tentative decision of the previous round, compacts the list
+ *         of still-active frames on the device and runs in chunks of rounds. */
+enum { LDPC_FD_MODE_PLAIN = 0, LDPC_FD_MODE_FUSED = 1 };
+
+/* status[f] bits */
+#define LDPC_FD_STATUS_CONVERGED 1u /* stopped on a passed codeword test */
+#define LDPC_FD_STATUS_MISMATCH 2u  /* Fourier and direct syndromes differed at some round */
+
+/* Create a code object (Sec. 2: the code {x : Hx = 0}).
+ * M, N: H is M x N.  m: field GF(2^m), 2 <= m <= 8.
+ * row_ptr[M+1], col[E], val[E]: host arrays, copied; E = row_ptr[M].
+ *   val[e] in 1..2^m-1 is h_cv in the integer representation above.
+ * prim_poly: primitive polynomial with bit m set (0 selects the default:
+ *   x^2+x+1, x^3+x+1, x^4+x+1, x^5+x^2+1, x^6+x+1, x^7+x^3+1,
+ *   x^8+x^4+x^3+x^2+1).
+ * out: receives the handle; owns device tables until ldpc_fd_destroy_code.
+ * Errors: E_INVALID (bad CSR, label 0 or >= 2^m, duplicate (c,v), row weight
+ *   < 2, non-primitive prim_poly), E_UNSUPPORTED (a column weight != 2, m
+ *   outside 2..8, row weight > 16), E_HIP / E_NOMEM on device allocation. */
+int32_t ldpc_fd_create_code(int32_t M, int32_t N, int32_t m, const int32_t *row_ptr,
+                            const int32_t *col, const uint16_t *val, uint32_t prim_poly,
+                            ldpc_fd_code *out);
+
+/* Release a code object and its device tables (NULL is a no-op). */
+int32_t ldpc_fd_destroy_code(ldpc_fd_code code);
+
+/* Shape of a code object; any output pointer may be NULL. */
+int32_t ldpc_fd_code_info(ldpc_fd_code code, int32_t *M, int32_t *N, int32_t *m, int32_t *E,
+                          int32_t *kmax);
+
+/* Bytes of caller-owned device workspace that ldpc_fd_decode needs for
+ * `frames` frames at storage precision `prec` in decoder variant `mode`. */
+int32_t ldpc_fd_workspace_bytes(ldpc_fd_code code, int32_t frames, int32_t prec, int32_t mode,
+                                int64_t *bytes);
+
+/* Decode a batch of frames (Sec. 3.2, the Log-Fourier SP algorithm, with the
+ * stopping rule of Sec. 2: stop at the first round whose tentative decision
+ * passes the codeword test, FAIL when the round count reaches max_iter).
+ *
+ * frames >= 0; llr: device [frames][N][m] FP32 (see above); max_iter >= 1.
+ * Outputs (device, caller-owned, written for every frame):
+ *   hard[frames][N]  uint8: bitwise-MAP tentative symbols of the stopping round,
+ *                    read from the signs of the Fourier-domain posterior at
+ *                    alpha^(i-1) (Sec. 3.1 Eq. (5), Sec. 3.2);
+ *   synd[frames][M]  uint8: direct syndrome H * hard (integer-exact);
+ *   iters[frames]    int32: round l at which the frame stopped, 1..max_iter;
+ *   status[frames]   uint32: LDPC_FD_STATUS_* bits.
+ * A frame stops when both its Fourier-domain syndrome (Sec. 3.1/3.2) and its
+ * direct syndrome are zero.
+ * workspace: device memory of at least ldpc_fd_workspace_bytes(...) bytes,
+ *   caller-owned, not retained after the call returns.
+ * The call is stream-ordered; it synchronises with the stream internally only
+ * to read the count of active frames between chunks of rounds.
+ * Errors: E_INVALID (null pointers with frames > 0, max_iter < 1, unknown
+ *   prec/mode), E_NOMEM (workspace too small), E_HIP. */
+int32_t ldpc_fd_decode(ldpc_fd_code code, int32_t frames, const float *llr, int32_t max_iter,
+                       int32_t prec, int32_t mode, uint8_t *hard, uint8_t *synd,
+                       int32_t *iters, uint32_t *status, void *workspace,
+                       int64_t workspace_bytes, void *stream);
+
+/* One flooding round from an imported state, for message-level parity checks
+ * (Sec. 3.2 VARIABLE TO CHECK, TENTATIVE DECISION, then CHECK TO VARIABLE):
+ *   from c2v_in = Lambda_cv^(l) (FP32 message layout above; NULL means round 0,
+ *   i.e. the variable-to-check messages are the initial messages Lambda_v^(0)),
+ *   writes v2c_out = Lambda_vc^(l) (normalised so that Lambda_vc(0) = (0,0);
+ *   required in PLAIN mode, must be NULL in FUSED mode, which never stores
+ *   variable-to-check messages), c2v_out = Lambda_cv^(l+1), and, when c2v_in is
+ *   not NULL, the
+ *   tentative decision of round l: hard[frames][N], fsynd[frames][M] (Fourier
+ *   syndrome words, bit i = syndrome bit i+1 of the check) and synd[frames][M]
+ *   (direct syndrome of hard).  All arrays are device memory; FP32 storage.
+ *   mode selects which kernels compute it (PLAIN or FUSED).
+ * Errors: E_INVALID, E_HIP. */
+int32_t ldpc_fd_round(ldpc_fd_code code, int32_t frames, const float *llr, const float *c2v_in,
+                      float *v2c_out, float *c2v_out, uint8_t *hard, uint8_t *fsynd,
+                      uint8_t *synd, int32_t mode, void *stream);
+
+/* Kernel timing for measurement (calling thread only).  While enabled,
+ * ldpc_fd_decode records a pair of HIP events on its stream around every launch
+ * of the per-round kernels: LDPC_FD_K_FUSED (the fused pass), LDPC_FD_K_CHECK
+ * and LDPC_FD_K_VAR (the PLAIN check-node and variable-node kernels).
+ * ldpc_fd_profile_read waits for the recorded events, returns the summed
+ * duration in milliseconds and the number of launches of `kernel`, and clears
+ * that kernel's record.  Errors: E_INVALID (unknown kernel), E_HIP. */
+enum { LDPC_FD_K_FUSED = 0, LDPC_FD_K_CHECK = 1, LDPC_FD_K_VAR = 2 };
+int32_t ldpc_fd_profile_enable(int32_t on);
+int32_t ldpc_fd_profile_read(int32_t kernel, double *ms, int64_t *launches);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *ldpc_fd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDPC_FD_H */

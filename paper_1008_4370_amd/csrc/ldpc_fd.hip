@@ -1,0 +1,502 @@
+// libldpcfd: C-ABI Log-Fourier SP decoder for (2,k) non-binary LDPC codes on
+// gfx950.  Entry points are declared and documented in include/ldpc_fd.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ldpc_fd.h"
+#include "lfsp_kernels.h"
+
+using namespace ldpcfd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(LDPC_FD_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+const uint32_t kDefaultPoly[9] = {0, 0x3, 0x7, 0xB, 0x13, 0x25, 0x43, 0x89, 0x11D};
+
+}  // namespace
+
+struct ldpc_fd_code_s {
+  int M = 0, N = 0, m = 0, q = 0, E = 0, kmax = 0;
+  uint32_t poly = 0;
+  int device = 0;
+  std::vector<void*> allocs;
+  DevCode dev{};
+  ~ldpc_fd_code_s() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+template <typename T>
+int32_t upload(ldpc_fd_code_s* c, const std::vector<T>& h, const T** out) {
+  void* d = nullptr;
+  const size_t bytes = std::max<size_t>(h.size() * sizeof(T), 16);
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return fail(LDPC_FD_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->allocs.push_back(d);
+  if (!h.empty()) HIP_TRY(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = static_cast<const T*>(d);
+  return LDPC_FD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel geometry selection.  Rows of weight <= 8 use 16 entries per lane
+// (L = Q/16 lanes per frame); heavier rows (<= 16) use 4 entries per lane so
+// that the per-check stash of k messages stays in registers.
+template <int LOGQ, int LOGR, int KMAX>
+struct Impl {
+  using G = Geo<LOGQ, LOGR>;
+  static constexpr int kWaves = 4;
+  static size_t lds() { return (size_t)kWaves * G::T * G::QP * sizeof(float); }
+  static unsigned blocks(long items) { return (unsigned)((items + kWaves - 1) / kWaves); }
+  static int frames_per_wave() { return G::T; }
+
+  static void var_plain(const DevCode& cd, int F, const float* llr, const float* c2v, float* v2c,
+                        uint8_t* hard, uint8_t* fsw, const uint32_t* active, int first, hipStream_t s) {
+    const long items = (long)((F + G::T - 1) / G::T) * cd.N;
+    if (items == 0) return;
+    hipLaunchKernelGGL(k_var_plain<G>, dim3(blocks(items)), dim3(64 * kWaves), lds(), s, cd, F, llr, c2v,
+                       v2c, hard, fsw, active, first);
+  }
+  static void check_plain(const DevCode& cd, int F, const float* v2c, float* c2v, const uint32_t* active,
+                          hipStream_t s) {
+    const long items = (long)((F + G::T - 1) / G::T) * cd.M;
+    if (items == 0) return;
+    hipLaunchKernelGGL((k_check_plain<G, KMAX>), dim3(blocks(items)), dim3(64 * kWaves), lds(), s, cd, F,
+                       v2c, c2v, active);
+  }
+  template <typename S>
+  static void fused(const DevCode& cd, int Fmax, const float* llr, const S* cin, S* cout, uint8_t* hard,
+                    uint8_t* fsw, const int* alist, const int* nact, int first, int decide, int write,
+                    hipStream_t s) {
+    const long items = (long)((Fmax + G::T - 1) / G::T) * cd.M;
+    if (items == 0) return;
+    hipLaunchKernelGGL((k_fused<G, KMAX, S>), dim3(blocks(items)), dim3(64 * kWaves), lds(), s, cd, llr,
+                       cin, cout, hard, fsw, alist, nact, first, decide, write);
+  }
+};
+
+template <int LOGQ, class Fn>
+bool dispatch_q(int kmax, Fn&& fn) {
+  constexpr int LOGR_SMALLK = LOGQ < 4 ? LOGQ : 4;
+  if (kmax <= 8) {
+    fn(Impl<LOGQ, LOGR_SMALLK, 8>{});
+    return true;
+  }
+  if (kmax <= 16) {
+    fn(Impl<LOGQ, 2, 16>{});
+    return true;
+  }
+  return false;
+}
+
+template <class Fn>
+bool dispatch(int m, int kmax, Fn&& fn) {
+  switch (m) {
+    case 2: return dispatch_q<2>(kmax, fn);
+    case 3: return dispatch_q<3>(kmax, fn);
+    case 4: return dispatch_q<4>(kmax, fn);
+    case 5: return dispatch_q<5>(kmax, fn);
+    case 6: return dispatch_q<6>(kmax, fn);
+    case 7: return dispatch_q<7>(kmax, fn);
+    case 8: return dispatch_q<8>(kmax, fn);
+    default: return false;
+  }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t msg_bytes(int prec) { return prec == LDPC_FD_FP32 ? 4 : 2; }
+
+// Workspace carving -------------------------------------------------------
+struct PlainWs {
+  float* v2c;
+  float* c2v;
+  uint8_t* fsw;
+  uint32_t* active;
+  uint32_t* unsat;
+  uint32_t* mism;
+  uint32_t* count;
+};
+struct FusedWs {
+  void* buf[2];
+  uint8_t* fsw;
+  int* alist;
+  int* tmp;
+  uint32_t* unsat;
+  uint32_t* mism;
+  int* nact;
+};
+
+size_t plain_layout(const ldpc_fd_code_s* c, int F, char* base, PlainWs* w) {
+  const size_t msg = align256((size_t)F * c->E * c->q * 4);
+  size_t off = 0;
+  auto take = [&](size_t n) { char* p = base ? base + off : nullptr; off += align256(n); return p; };
+  char* p0 = take(msg);
+  char* p1 = take(msg);
+  char* p2 = take((size_t)F * c->E);
+  char* p3 = take((size_t)F * 4);
+  char* p4 = take((size_t)F * 4);
+  char* p5 = take((size_t)F * 4);
+  char* p6 = take(4);
+  if (w) *w = PlainWs{(float*)p0, (float*)p1, (uint8_t*)p2, (uint32_t*)p3, (uint32_t*)p4, (uint32_t*)p5, (uint32_t*)p6};
+  return off;
+}
+
+size_t fused_layout(const ldpc_fd_code_s* c, int F, int prec, char* base, FusedWs* w) {
+  const size_t msg = align256((size_t)F * c->E * c->q * msg_bytes(prec));
+  size_t off = 0;
+  auto take = [&](size_t n) { char* p = base ? base + off : nullptr; off += align256(n); return p; };
+  char* b0 = take(msg);
+  char* b1 = take(msg);
+  char* p2 = take((size_t)F * c->E);
+  char* p3 = take((size_t)F * 4);
+  char* p4 = take((size_t)F * 4);
+  char* p5 = take((size_t)F * 4);
+  char* p6 = take((size_t)F * 4);
+  char* p7 = take(4);
+  if (w) *w = FusedWs{{b0, b1}, (uint8_t*)p2, (int*)p3, (int*)p4, (uint32_t*)p5, (uint32_t*)p6, (int*)p7};
+  return off;
+}
+
+thread_local int* t_pinned = nullptr;
+
+int32_t read_count(const void* dptr, hipStream_t s, int* out) {
+  if (!t_pinned) HIP_TRY(hipHostMalloc((void**)&t_pinned, 64, hipHostMallocDefault));
+  HIP_TRY(hipMemcpyAsync(t_pinned, dptr, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = *t_pinned;
+  return LDPC_FD_OK;
+}
+
+unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// Per-thread kernel timing (ldpc_fd_profile_*).
+struct Profile {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) {
+      e = pool.back();
+      pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+};
+thread_local Profile t_prof;
+
+// Run `launch` on stream s, bracketed by events when profiling is on.
+template <class Fn>
+void timed(int kernel, hipStream_t s, Fn&& launch) {
+  if (!t_prof.on) {
+    launch();
+    return;
+  }
+  hipEvent_t a = t_prof.get(), b = t_prof.get();
+  if (a) (void)hipEventRecord(a, s);
+  launch();
+  if (b) (void)hipEventRecord(b, s);
+  if (a && b) t_prof.ev[kernel].emplace_back(a, b);
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* ldpc_fd_last_error(void) { return g_err.c_str(); }
+
+int32_t ldpc_fd_create_code(int32_t M, int32_t N, int32_t m, const int32_t* row_ptr, const int32_t* col,
+                            const uint16_t* val, uint32_t prim_poly, ldpc_fd_code* out) {
+  if (!out) return fail(LDPC_FD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (m < 2 || m > 8) return fail(LDPC_FD_E_UNSUPPORTED, "m must be in 2..8");
+  if (M < 1 || N < 1 || !row_ptr || !col || !val) return fail(LDPC_FD_E_INVALID, "bad shape or NULL array");
+  const int q = 1 << m;
+  if (row_ptr[0] != 0) return fail(LDPC_FD_E_INVALID, "row_ptr[0] != 0");
+  for (int c = 0; c < M; ++c)
+    if (row_ptr[c + 1] < row_ptr[c]) return fail(LDPC_FD_E_INVALID, "row_ptr not nondecreasing");
+  const int E = row_ptr[M];
+  if (E != 2 * N) {
+    // column weights are checked below; E = 2N is implied by weight 2
+  }
+  std::vector<int> colw(N, 0);
+  int kmax = 0;
+  for (int c = 0; c < M; ++c) {
+    const int d = row_ptr[c + 1] - row_ptr[c];
+    if (d < 2) return fail(LDPC_FD_E_INVALID, "row " + std::to_string(c) + " has weight < 2");
+    kmax = std::max(kmax, d);
+    for (int e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
+      if (col[e] < 0 || col[e] >= N) return fail(LDPC_FD_E_INVALID, "column index out of range");
+      if (val[e] == 0 || val[e] >= q) return fail(LDPC_FD_E_INVALID, "label outside 1..2^m-1");
+      for (int e2 = row_ptr[c]; e2 < e; ++e2)
+        if (col[e2] == col[e]) return fail(LDPC_FD_E_INVALID, "duplicate entry (c,v)");
+      colw[col[e]]++;
+    }
+  }
+  for (int v = 0; v < N; ++v)
+    if (colw[v] != 2)
+      return fail(LDPC_FD_E_UNSUPPORTED, "column " + std::to_string(v) + " has weight " + std::to_string(colw[v]) + " (need 2)");
+  if (kmax > 16) return fail(LDPC_FD_E_UNSUPPORTED, "row weight above 16");
+  const uint32_t poly = prim_poly ? prim_poly : kDefaultPoly[m];
+  if ((poly >> m) != 1u) return fail(LDPC_FD_E_INVALID, "prim_poly must have degree m");
+  // field tables from the primitive polynomial (alpha = x)
+  std::vector<uint8_t> gexp(512, 0);
+  std::vector<uint16_t> glog(256, 0);
+  {
+    uint32_t x = 1;
+    for (int i = 0; i < q - 1; ++i) {
+      if (i > 0 && x == 1) return fail(LDPC_FD_E_INVALID, "prim_poly is not primitive");
+      gexp[i] = (uint8_t)x;
+      glog[x] = (uint16_t)i;
+      x <<= 1;
+      if (x & (uint32_t)q) x ^= poly;
+    }
+    if (x != 1) return fail(LDPC_FD_E_INVALID, "prim_poly is not primitive");
+    for (int i = q - 1; i < 512; ++i) gexp[i] = gexp[i % (q - 1)];
+  }
+  auto gmul = [&](int a, int b) -> int { return (a && b) ? gexp[(glog[a] + glog[b]) % (q - 1)] : 0; };
+  std::vector<uint8_t> ginv(256, 0);
+  std::vector<uint64_t> colsT(256, 0);
+  for (int h = 1; h < q; ++h) {
+    ginv[h] = (uint8_t)gexp[(q - 1 - glog[h]) % (q - 1)];
+    uint64_t w = 0;
+    for (int b = 0; b < m; ++b) {  // M_h^T e_b = row b of M_h, column j = bits of h*alpha^j
+      int rowb = 0;
+      for (int j = 0; j < m; ++j) rowb |= ((gmul(h, 1 << j) >> b) & 1) << j;
+      w |= (uint64_t)rowb << (8 * b);
+    }
+    colsT[h] = w;
+  }
+  // graph tables
+  std::vector<int> rp(row_ptr, row_ptr + M + 1), ev(col, col + E), eo(E, -1), ve(2 * N, -1);
+  std::vector<uint8_t> el(E);
+  for (int e = 0; e < E; ++e) el[e] = (uint8_t)val[e];
+  std::vector<int> fill(N, 0);
+  for (int e = 0; e < E; ++e) ve[2 * col[e] + fill[col[e]]++] = e;  // ascending e per variable
+  for (int v = 0; v < N; ++v) {
+    eo[ve[2 * v]] = ve[2 * v + 1];
+    eo[ve[2 * v + 1]] = ve[2 * v];
+  }
+  auto* c = new (std::nothrow) ldpc_fd_code_s();
+  if (!c) return fail(LDPC_FD_E_NOMEM, "host allocation failed");
+  c->M = M; c->N = N; c->m = m; c->q = q; c->E = E; c->kmax = kmax; c->poly = poly;
+  hipGetDevice(&c->device);
+  DevCode& d = c->dev;
+  d.M = M; d.N = N; d.E = E; d.m = m;
+  int32_t rc;
+  if ((rc = upload(c, rp, &d.row_ptr)) || (rc = upload(c, ev, &d.e_var)) || (rc = upload(c, eo, &d.e_other)) ||
+      (rc = upload(c, el, &d.e_label)) || (rc = upload(c, ve, &d.v_edges)) || (rc = upload(c, colsT, &d.colsT)) ||
+      (rc = upload(c, ginv, &d.ginv)) || (rc = upload(c, gexp, &d.gexp)) || (rc = upload(c, glog, &d.glog))) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return LDPC_FD_OK;
+}
+
+int32_t ldpc_fd_destroy_code(ldpc_fd_code code) {
+  delete code;
+  return LDPC_FD_OK;
+}
+
+int32_t ldpc_fd_code_info(ldpc_fd_code c, int32_t* M, int32_t* N, int32_t* m, int32_t* E, int32_t* kmax) {
+  if (!c) return fail(LDPC_FD_E_INVALID, "code is NULL");
+  if (M) *M = c->M;
+  if (N) *N = c->N;
+  if (m) *m = c->m;
+  if (E) *E = c->E;
+  if (kmax) *kmax = c->kmax;
+  return LDPC_FD_OK;
+}
+
+int32_t ldpc_fd_workspace_bytes(ldpc_fd_code c, int32_t frames, int32_t prec, int32_t mode, int64_t* bytes) {
+  if (!c || !bytes || frames < 0) return fail(LDPC_FD_E_INVALID, "bad argument");
+  if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
+  if (mode == LDPC_FD_MODE_PLAIN) {
+    if (prec != LDPC_FD_FP32) return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN decoder stores FP32 messages only");
+    *bytes = (int64_t)plain_layout(c, frames, nullptr, nullptr);
+  } else if (mode == LDPC_FD_MODE_FUSED) {
+    *bytes = (int64_t)fused_layout(c, frames, prec, nullptr, nullptr);
+  } else {
+    return fail(LDPC_FD_E_INVALID, "unknown mode");
+  }
+  return LDPC_FD_OK;
+}
+
+int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_iter, int32_t prec, int32_t mode,
+                       uint8_t* hard, uint8_t* synd, int32_t* iters, uint32_t* status, void* workspace,
+                       int64_t workspace_bytes, void* stream) {
+  if (!c) return fail(LDPC_FD_E_INVALID, "code is NULL");
+  if (F < 0 || max_iter < 1) return fail(LDPC_FD_E_INVALID, "frames < 0 or max_iter < 1");
+  if (F == 0) return LDPC_FD_OK;
+  if (!llr || !hard || !synd || !iters || !status || !workspace) return fail(LDPC_FD_E_INVALID, "NULL buffer");
+  int64_t need = 0;
+  int32_t rc = ldpc_fd_workspace_bytes(c, F, prec, mode, &need);
+  if (rc) return rc;
+  if (workspace_bytes < need) return fail(LDPC_FD_E_NOMEM, "workspace too small: need " + std::to_string(need));
+  hipStream_t s = (hipStream_t)stream;
+  const DevCode& cd = c->dev;
+  const unsigned fb = cdiv(F, 256);
+  if (mode == LDPC_FD_MODE_PLAIN) {
+    PlainWs w;
+    plain_layout(c, F, (char*)workspace, &w);
+    hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, w.active, w.unsat, w.mism, (int*)nullptr,
+                       (int*)nullptr, iters, status);
+    bool ok = dispatch(c->m, c->kmax, [&](auto impl) {
+      using I = decltype(impl);
+      timed(LDPC_FD_K_VAR, s, [&] { I::var_plain(cd, F, llr, nullptr, w.v2c, hard, w.fsw, w.active, 1, s); });
+    });
+    if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+    for (int ell = 1; ell <= max_iter; ++ell) {
+      dispatch(c->m, c->kmax, [&](auto impl) {
+        using I = decltype(impl);
+        timed(LDPC_FD_K_CHECK, s, [&] { I::check_plain(cd, F, w.v2c, w.c2v, w.active, s); });
+        timed(LDPC_FD_K_VAR, s, [&] { I::var_plain(cd, F, llr, w.c2v, w.v2c, hard, w.fsw, w.active, 0, s); });
+      });
+      hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, cd, hard, w.fsw, synd,
+                         (uint8_t*)nullptr, w.unsat, w.mism, (const int*)nullptr, (const int*)nullptr, F,
+                         w.active);
+      HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
+      hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,
+                         iters, status, w.count);
+      int left = 0;
+      if ((rc = read_count(w.count, s, &left))) return rc;
+      if (left == 0) break;
+    }
+    HIP_TRY(hipGetLastError());
+    return LDPC_FD_OK;
+  }
+  if (mode != LDPC_FD_MODE_FUSED) return fail(LDPC_FD_E_INVALID, "unknown mode");
+  FusedWs w;
+  fused_layout(c, F, prec, (char*)workspace, &w);
+  hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, (uint32_t*)nullptr, w.unsat, w.mism, w.alist,
+                     w.nact, iters, status);
+  const int chunk = 4;
+  auto run_pass = [&](int first, int decide, int write, const void* cin, void* cout) {
+    return dispatch(c->m, c->kmax, [&](auto impl) {
+      using I = decltype(impl);
+      timed(LDPC_FD_K_FUSED, s, [&] {
+      if (prec == LDPC_FD_FP32)
+        I::template fused<float>(cd, F, llr, (const float*)cin, (float*)cout, hard, w.fsw, w.alist, w.nact, first,
+                                 decide, write, s);
+      else if (prec == LDPC_FD_FP16)
+        I::template fused<_Float16>(cd, F, llr, (const _Float16*)cin, (_Float16*)cout, hard, w.fsw, w.alist,
+                                    w.nact, first, decide, write, s);
+      else
+        I::template fused<bf16_t>(cd, F, llr, (const bf16_t*)cin, (bf16_t*)cout, hard, w.fsw, w.alist, w.nact,
+                                  first, decide, write, s);
+      });
+    });
+  };
+  if (!run_pass(1, 0, 1, nullptr, w.buf[1])) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+  for (int ell = 1; ell <= max_iter; ++ell) {
+    run_pass(0, 1, ell < max_iter, w.buf[ell & 1], w.buf[(ell + 1) & 1]);
+    hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, cd, hard, w.fsw, synd,
+                       (uint8_t*)nullptr, w.unsat, w.mism, w.alist, w.nact, F, (const uint32_t*)nullptr);
+    hipLaunchKernelGGL(k_retire_compact, dim3(1), dim3(1024), 0, s, ell, max_iter, w.alist, w.tmp, w.nact, w.unsat,
+                       w.mism, iters, status);
+    if (ell % chunk == 0 || ell == max_iter) {
+      int left = 0;
+      if ((rc = read_count(w.nact, s, &left))) return rc;
+      if (left == 0) break;
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return LDPC_FD_OK;
+}
+
+int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* c2v_in, float* v2c_out,
+                      float* c2v_out, uint8_t* hard, uint8_t* fsynd, uint8_t* synd, int32_t mode, void* stream) {
+  if (!c) return fail(LDPC_FD_E_INVALID, "code is NULL");
+  if (F < 0) return fail(LDPC_FD_E_INVALID, "frames < 0");
+  if (F == 0) return LDPC_FD_OK;
+  if (!llr || !c2v_out) return fail(LDPC_FD_E_INVALID, "NULL llr or c2v_out");
+  if (c2v_in && (!hard || !fsynd || !synd)) return fail(LDPC_FD_E_INVALID, "decision outputs required");
+  if (mode == LDPC_FD_MODE_PLAIN && !v2c_out) return fail(LDPC_FD_E_INVALID, "PLAIN round needs v2c_out");
+  if (mode == LDPC_FD_MODE_FUSED && v2c_out) return fail(LDPC_FD_E_INVALID, "FUSED round does not form v2c_out");
+  if (mode != LDPC_FD_MODE_PLAIN && mode != LDPC_FD_MODE_FUSED) return fail(LDPC_FD_E_INVALID, "unknown mode");
+  hipStream_t s = (hipStream_t)stream;
+  const DevCode& cd = c->dev;
+  char* tmp = nullptr;
+  const size_t n_fsw = align256((size_t)F * c->E), n4 = align256((size_t)F * 4);
+  HIP_TRY(hipMalloc((void**)&tmp, n_fsw + 4 * n4 + 256));
+  uint8_t* fsw = (uint8_t*)tmp;
+  uint32_t* active = (uint32_t*)(tmp + n_fsw);
+  uint32_t* unsat = (uint32_t*)(tmp + n_fsw + n4);
+  uint32_t* mism = (uint32_t*)(tmp + n_fsw + 2 * n4);
+  int* alist = (int*)(tmp + n_fsw + 3 * n4);
+  int* nact = (int*)(tmp + n_fsw + 4 * n4);
+  const unsigned fb = cdiv(F, 256);
+  hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, active, unsat, mism, alist, nact, (int32_t*)nullptr,
+                     (uint32_t*)nullptr);
+  bool ok = dispatch(c->m, c->kmax, [&](auto impl) {
+    using I = decltype(impl);
+    if (mode == LDPC_FD_MODE_PLAIN) {
+      I::var_plain(cd, F, llr, c2v_in, v2c_out, hard, fsw, nullptr, c2v_in ? 0 : 1, s);
+      if (c2v_in)
+        hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, cd, hard, fsw, synd, fsynd,
+                           unsat, mism, (const int*)nullptr, (const int*)nullptr, F, (const uint32_t*)nullptr);
+      I::check_plain(cd, F, v2c_out, c2v_out, nullptr, s);
+    } else {
+      I::template fused<float>(cd, F, llr, c2v_in, c2v_out, hard, fsw, alist, nact, c2v_in ? 0 : 1,
+                               c2v_in ? 1 : 0, 1, s);
+      if (c2v_in)
+        hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, cd, hard, fsw, synd, fsynd,
+                           unsat, mism, alist, nact, F, (const uint32_t*)nullptr);
+    }
+  });
+  hipError_t e1 = hipStreamSynchronize(s);
+  hipError_t e2 = hipFree(tmp);
+  if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+  if (e1 != hipSuccess) return fail(LDPC_FD_E_HIP, std::string("round: ") + hipGetErrorString(e1));
+  if (e2 != hipSuccess) return fail(LDPC_FD_E_HIP, std::string("hipFree: ") + hipGetErrorString(e2));
+  return LDPC_FD_OK;
+}
+
+int32_t ldpc_fd_profile_enable(int32_t on) {
+  t_prof.on = on != 0;
+  return LDPC_FD_OK;
+}
+
+int32_t ldpc_fd_profile_read(int32_t kernel, double* ms, int64_t* launches) {
+  if (kernel < 0 || kernel > 2) return fail(LDPC_FD_E_INVALID, "unknown kernel id");
+  double total = 0.0;
+  int64_t n = 0;
+  for (auto& pr : t_prof.ev[kernel]) {
+    HIP_TRY(hipEventSynchronize(pr.second));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, pr.first, pr.second));
+    total += t;
+    ++n;
+    t_prof.pool.push_back(pr.first);
+    t_prof.pool.push_back(pr.second);
+  }
+  t_prof.ev[kernel].clear();
+  if (ms) *ms = total;
+  if (launches) *launches = n;
+  return LDPC_FD_OK;
+}
+
+}  // extern "C"

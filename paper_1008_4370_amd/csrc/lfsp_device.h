@@ -1,0 +1,231 @@
+// Device building blocks of the Log-Fourier SP decoder (gfx950, wave64).
+//
+// A message is a length-Q vector (Q = 2^m).  A wavefront holds T = 64/L
+// frames; each frame's vector is spread over L consecutive lanes with R = Q/L
+// entries per lane.  Entry (lane-in-frame zl, register r) holds index
+//     z = (r & 3) | (zl << 2) | ((r >> 2) << (2 + log2 L)),
+// so each lane owns runs of 4 consecutive z (one 16-byte FP32 load), z bits
+// 0-1 and the high bits live in registers and bits 2..2+log2(L)-1 across the
+// frame's lanes.  Butterflies along register bits are plain VALU; along lane
+// bits they use DPP quad permutes (lane xor 1, 2) or ds_swizzle (xor 4..16).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ldpcfd {
+
+// Largest stored magnitude -log2|P| (|P| >= 2^-100 is kept, smaller is 2^-100).
+constexpr float kLmax = 100.0f;
+
+template <int LOGQ_, int LOGR_>
+struct Geo {
+  static constexpr int LOGQ = LOGQ_;
+  static constexpr int Q = 1 << LOGQ;
+  static constexpr int LOGR = LOGR_;
+  static constexpr int R = 1 << LOGR;
+  static constexpr int LOGL = LOGQ - LOGR;
+  static constexpr int L = 1 << LOGL;
+  static constexpr int T = 64 / L;
+  static constexpr int QP = Q + 4;  // LDS row pitch in floats (16-byte aligned rows)
+  static_assert(LOGR >= 2 && LOGL >= 0 && LOGL <= 6, "bad geometry");
+  static __host__ __device__ constexpr bool lane_bit(int b) { return b >= 2 && b < 2 + LOGL; }
+  static __host__ __device__ constexpr int lane_shift(int b) { return b - 2; }
+  static __host__ __device__ constexpr int reg_bit(int b) { return b < 2 ? b : b - LOGL; }
+  static __host__ __device__ constexpr int zbit_of_regbit(int rb) { return rb < 2 ? rb : rb + LOGL; }
+  static __device__ __forceinline__ int z_of(int zl, int r) {
+    return (r & 3) | (zl << 2) | ((r >> 2) << (2 + LOGL));
+  }
+};
+
+__device__ __forceinline__ int lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Value held by lane (this lane xor mask); mask is a compile-time constant
+// after unrolling.
+__device__ __forceinline__ float lane_xor(float v, int mask) {
+  const int iv = __float_as_int(v);
+  switch (mask) {
+    case 1:
+      return __int_as_float(__builtin_amdgcn_mov_dpp(iv, 0xB1, 0xF, 0xF, false));
+    case 2:
+      return __int_as_float(__builtin_amdgcn_mov_dpp(iv, 0x4E, 0xF, 0xF, false));
+    case 4:
+      return __int_as_float(__builtin_amdgcn_ds_swizzle(iv, (4 << 10) | 0x1F));
+    case 8:
+      return __int_as_float(__builtin_amdgcn_ds_swizzle(iv, (8 << 10) | 0x1F));
+    case 16:
+      return __int_as_float(__builtin_amdgcn_ds_swizzle(iv, (16 << 10) | 0x1F));
+    default:
+      return __int_as_float(__builtin_amdgcn_ds_bpermute((lane_id() ^ 32) << 2, iv));
+  }
+}
+
+// Broadcast the value of the frame's first lane (zl = 0) to its L lanes.
+template <class G>
+__device__ __forceinline__ float bcast_frame0(float v) {
+  const int iv = __float_as_int(v);
+  if constexpr (G::L == 1) {
+    return v;
+  } else if constexpr (G::L == 2) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(iv, 0xA0, 0xF, 0xF, false));  // [0,0,2,2]
+  } else if constexpr (G::L == 4) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(iv, 0x00, 0xF, 0xF, false));  // [0,0,0,0]
+  } else {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute((lane_id() & ~(G::L - 1)) << 2, iv));
+  }
+}
+
+// ---- signed-log map (Sec. 3.2): word = sign bit | -log2|P| --------------------
+__device__ __forceinline__ float gamma_inv(float w) {
+  const float a = __builtin_amdgcn_exp2f(-__builtin_fabsf(w));
+  return __uint_as_float((__float_as_uint(w) & 0x80000000u) | __float_as_uint(a));
+}
+
+// Gamma of P / P0 given lg0 = log2(P0) > -inf: magnitude clamped to [0, kLmax].
+__device__ __forceinline__ float gamma_rel(float p, float lg0) {
+  const float mag = __builtin_amdgcn_fmed3f(lg0 - __builtin_amdgcn_logf(__builtin_fabsf(p)), 0.0f, kLmax);
+  return __uint_as_float((__float_as_uint(p) & 0x80000000u) | __float_as_uint(mag));
+}
+
+// ---- XOR convolution with the channel prior in the Fourier domain -------------
+// The prior of a BPSK symbol is a product over its bits, so its Fourier image is
+// P0(z) = prod_{i in z} t_i with t_i = tanh(L_i / 2), and P0 (*) X factors into
+// one two-point step per bit: X(z) <- X(z) + t_i X(z xor e_i).
+template <class G>
+__device__ __forceinline__ void conv_prior(float (&v)[G::R], const float (&t)[G::LOGQ]) {
+#pragma unroll
+  for (int b = 0; b < G::LOGQ; ++b) {
+    const float tb = t[b];
+    if (G::lane_bit(b)) {
+      const int mask = 1 << G::lane_shift(b);
+#pragma unroll
+      for (int r = 0; r < G::R; ++r) v[r] = __builtin_fmaf(tb, lane_xor(v[r], mask), v[r]);
+    } else {
+      const int rb = 1 << G::reg_bit(b);
+#pragma unroll
+      for (int r = 0; r < G::R; ++r) {
+        if (!(r & rb)) {
+          const float a = v[r], c = v[r | rb];
+          v[r] = __builtin_fmaf(tb, c, a);
+          v[r | rb] = __builtin_fmaf(tb, a, c);
+        }
+      }
+    }
+  }
+}
+
+// ---- unnormalised Walsh-Hadamard transform: V(z) = sum_x v(x) (-1)^(z.x) ------
+template <class G>
+__device__ __forceinline__ void wht(float (&v)[G::R], int zl) {
+#pragma unroll
+  for (int b = 0; b < G::LOGQ; ++b) {
+    if (G::lane_bit(b)) {
+      const int sh = G::lane_shift(b);
+      const float s = ((zl >> sh) & 1) ? -1.0f : 1.0f;
+#pragma unroll
+      for (int r = 0; r < G::R; ++r) v[r] = __builtin_fmaf(s, v[r], lane_xor(v[r], 1 << sh));
+    } else {
+      const int rb = 1 << G::reg_bit(b);
+#pragma unroll
+      for (int r = 0; r < G::R; ++r) {
+        if (!(r & rb)) {
+          const float a = v[r], c = v[r | rb];
+          v[r] = a + c;
+          v[r | rb] = a - c;
+        }
+      }
+    }
+  }
+}
+
+// ---- label permutation through LDS -------------------------------------------
+// out(z) = in(A z) for a GF(2)-linear map A given by its columns col[b] = A e_b
+// (a wave-uniform 8-byte word, byte b).  `row` is this lane's frame row in LDS.
+// Lanes of one frame exchange entries through the frame's LDS row; LDS
+// operations of a wave execute in order, and wave barriers keep the compiler
+// from moving a lane's accesses across the exchange.
+template <class G>
+__device__ __forceinline__ void permute(float (&v)[G::R], float* row, int zl, uint64_t cols) {
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) row[G::z_of(zl, r)] = v[r];
+  __builtin_amdgcn_wave_barrier();
+  int pl = 0;
+#pragma unroll
+  for (int lb = 0; lb < G::LOGL; ++lb)
+    if ((zl >> lb) & 1) pl ^= (int)((cols >> (8 * (2 + lb))) & 0xFF);
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) {
+    int pr = 0;
+#pragma unroll
+    for (int rb = 0; rb < G::LOGR; ++rb)
+      if ((r >> rb) & 1) pr ^= (int)((cols >> (8 * G::zbit_of_regbit(rb))) & 0xFF);
+    v[r] = row[pr ^ pl];
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ---- message storage ------------------------------------------------------------
+struct bf16_t {
+  uint16_t bits;
+};
+
+template <typename S>
+struct IO;
+template <>
+struct IO<float> {
+  static __device__ __forceinline__ void load4(const float* p, float* o) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    o[0] = x.x; o[1] = x.y; o[2] = x.z; o[3] = x.w;
+  }
+  static __device__ __forceinline__ void store4(float* p, const float* i) {
+    *reinterpret_cast<float4*>(p) = make_float4(i[0], i[1], i[2], i[3]);
+  }
+};
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+template <>
+struct IO<_Float16> {
+  static __device__ __forceinline__ void load4(const _Float16* p, float* o) {
+    const half4_t x = *reinterpret_cast<const half4_t*>(p);
+    o[0] = (float)x[0]; o[1] = (float)x[1]; o[2] = (float)x[2]; o[3] = (float)x[3];
+  }
+  static __device__ __forceinline__ void store4(_Float16* p, const float* i) {
+    half4_t x;
+    x[0] = (_Float16)i[0]; x[1] = (_Float16)i[1]; x[2] = (_Float16)i[2]; x[3] = (_Float16)i[3];
+    *reinterpret_cast<half4_t*>(p) = x;
+  }
+};
+__device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;  // magnitudes here are finite
+}
+template <>
+struct IO<bf16_t> {
+  static __device__ __forceinline__ void load4(const bf16_t* p, float* o) {
+    const uint2 x = *reinterpret_cast<const uint2*>(p);
+    o[0] = __uint_as_float(x.x << 16); o[1] = __uint_as_float(x.x & 0xFFFF0000u);
+    o[2] = __uint_as_float(x.y << 16); o[3] = __uint_as_float(x.y & 0xFFFF0000u);
+  }
+  static __device__ __forceinline__ void store4(bf16_t* p, const float* i) {
+    uint2 x;
+    x.x = f32_to_bf16_rne(i[0]) | (f32_to_bf16_rne(i[1]) << 16);
+    x.y = f32_to_bf16_rne(i[2]) | (f32_to_bf16_rne(i[3]) << 16);
+    *reinterpret_cast<uint2*>(p) = x;
+  }
+};
+
+// Load / store one message (this lane's R entries) at `base` = start of the
+// frame's Q-vector for one edge.
+template <class G, typename S>
+__device__ __forceinline__ void load_msg(const S* base, int zl, float (&v)[G::R]) {
+#pragma unroll
+  for (int h = 0; h < G::R / 4; ++h) IO<S>::load4(base + 4 * zl + 4 * G::L * h, &v[4 * h]);
+}
+template <class G, typename S>
+__device__ __forceinline__ void store_msg(S* base, int zl, const float (&v)[G::R]) {
+#pragma unroll
+  for (int h = 0; h < G::R / 4; ++h) IO<S>::store4(base + 4 * zl + 4 * G::L * h, &v[4 * h]);
+}
+
+}  // namespace ldpcfd

@@ -1,0 +1,178 @@
+"""ctypes binding of libldpcfd.so (see include/ldpc_fd.h for the contract).
+
+Argument marshalling only: every step of decoding runs in the library's HIP
+kernels.  PyTorch supplies device buffers and the current HIP stream.  Loading
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libldpcfd.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "ldpc_fd.h")
+
+OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP = 0, -1, -2, -3, -4
+PREC = {"fp32": 0, "fp16": 1, "bf16": 2}
+MODE = {"plain": 0, "fused": 1}
+STATUS_CONVERGED, STATUS_MISMATCH = 1, 2
+K_FUSED, K_CHECK, K_VAR = 0, 1, 2
+
+_lib = None
+_c_void_p, _i32, _i64, _u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+
+_SIGS = {
+    "ldpc_fd_create_code": (_i32, [_i32, _i32, _i32, _c_void_p, _c_void_p, _c_void_p, _u32, ctypes.POINTER(_c_void_p)]),
+    "ldpc_fd_destroy_code": (_i32, [_c_void_p]),
+    "ldpc_fd_code_info": (_i32, [_c_void_p] + [ctypes.POINTER(_i32)] * 5),
+    "ldpc_fd_workspace_bytes": (_i32, [_c_void_p, _i32, _i32, _i32, ctypes.POINTER(_i64)]),
+    "ldpc_fd_decode": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _i32, _i32, _c_void_p, _c_void_p, _c_void_p,
+                              _c_void_p, _c_void_p, _i64, _c_void_p]),
+    "ldpc_fd_round": (_i32, [_c_void_p, _i32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                             _c_void_p, _i32, _c_void_p]),
+    "ldpc_fd_profile_enable": (_i32, [_i32]),
+    "ldpc_fd_profile_read": (_i32, [_i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
+    "ldpc_fd_last_error": (ctypes.c_char_p, []),
+}
+
+
+class LdpcFdError(RuntimeError):
+    def __init__(self, rc, msg):
+        super().__init__(f"libldpcfd error {rc}: {msg}")
+        self.rc = rc
+
+
+def lib():
+    """Load libldpcfd.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                               "python -m paper_1008_4370_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions declared in include/ldpc_fd.h."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ldpc_fd_\w+)\s*\(", text, re.M)))
+
+
+def _check(rc):
+    if rc != OK:
+        raise LdpcFdError(rc, lib().ldpc_fd_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Code:
+    """A code object on the current HIP device (Sec. 2: {x : Hx = 0})."""
+
+    def __init__(self, M, N, m, row_ptr, col, val, poly: int = 0):
+        self.M, self.N, self.m = int(M), int(N), int(m)
+        self._rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        self._col = np.ascontiguousarray(col, dtype=np.int32)
+        self._val = np.ascontiguousarray(val, dtype=np.uint16)
+        h = ctypes.c_void_p()
+        _check(lib().ldpc_fd_create_code(self.M, self.N, self.m, self._rp.ctypes.data, self._col.ctypes.data,
+                                         self._val.ctypes.data, int(poly), ctypes.byref(h)))
+        self.handle = h
+        vals = [_i32() for _ in range(5)]
+        _check(lib().ldpc_fd_code_info(self.handle, *[ctypes.byref(v) for v in vals]))
+        self.E, self.kmax = vals[3].value, vals[4].value
+        self.q = 1 << self.m
+
+    @classmethod
+    def from_synth(cls, code):
+        return cls(code.M, code.N, code.m, code.row_ptr, code.col, code.val, code.poly)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ldpc_fd_destroy_code(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_bytes(code: Code, frames: int, prec: str = "fp32", mode: str = "fused") -> int:
+    out = _i64()
+    _check(lib().ldpc_fd_workspace_bytes(code.handle, int(frames), PREC[prec], MODE[mode], ctypes.byref(out)))
+    return out.value
+
+
+class Decoder:
+    """Reusable decode context: output tensors and workspace for up to `frames`."""
+
+    def __init__(self, code: Code, frames: int, prec: str = "fp32", mode: str = "fused", device="cuda"):
+        import torch
+        self.code, self.frames, self.prec, self.mode = code, int(frames), prec, mode
+        F = self.frames
+        self.ws_bytes = workspace_bytes(code, F, prec, mode)
+        self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        self.hard = torch.empty((F, code.N), dtype=torch.uint8, device=device)
+        self.synd = torch.empty((F, code.M), dtype=torch.uint8, device=device)
+        self.iters = torch.empty((F,), dtype=torch.int32, device=device)
+        self.status = torch.empty((F,), dtype=torch.int32, device=device)
+
+    def __call__(self, llr, max_iter: int):
+        """llr: device float32 [F, N, m] (F <= frames).  Returns views of the outputs."""
+        F = llr.shape[0]
+        assert F <= self.frames and llr.is_contiguous() and llr.dtype.itemsize == 4
+        assert tuple(llr.shape[1:]) == (self.code.N, self.code.m)
+        _check(lib().ldpc_fd_decode(self.code.handle, F, _ptr(llr), int(max_iter), PREC[self.prec],
+                                    MODE[self.mode], _ptr(self.hard), _ptr(self.synd), _ptr(self.iters),
+                                    _ptr(self.status), _ptr(self.workspace), self.ws_bytes, _stream()))
+        return dict(hard=self.hard[:F], synd=self.synd[:F], iters=self.iters[:F], status=self.status[:F])
+
+
+def decode(code: Code, llr, max_iter: int, prec: str = "fp32", mode: str = "fused"):
+    """One-shot decode of device LLRs [F, N, m] (allocates its own buffers)."""
+    return Decoder(code, llr.shape[0], prec, mode, device=llr.device)(llr, max_iter)
+
+
+def round_step(code: Code, llr, c2v_in=None, mode: str = "plain"):
+    """One flooding round from an imported FP32 state (ldpc_fd_round)."""
+    import torch
+    F = llr.shape[0]
+    dev = llr.device
+    c2v_out = torch.empty((F, code.E, code.q), dtype=torch.float32, device=dev)
+    v2c_out = torch.empty_like(c2v_out) if mode == "plain" else None
+    hard = torch.zeros((F, code.N), dtype=torch.uint8, device=dev)
+    fsynd = torch.zeros((F, code.M), dtype=torch.uint8, device=dev)
+    synd = torch.zeros((F, code.M), dtype=torch.uint8, device=dev)
+    _check(lib().ldpc_fd_round(code.handle, F, _ptr(llr), _ptr(c2v_in), _ptr(v2c_out), _ptr(c2v_out),
+                               _ptr(hard), _ptr(fsynd), _ptr(synd), MODE[mode], _stream()))
+    return dict(c2v=c2v_out, v2c=v2c_out, hard=hard, fsynd=fsynd, synd=synd)
+
+
+def profile_enable(on: bool = True):
+    _check(lib().ldpc_fd_profile_enable(1 if on else 0))
+
+
+def profile_read(kernel: int):
+    """(total milliseconds, launches) of a per-round kernel since the last read."""
+    ms, n = ctypes.c_double(), _i64()
+    _check(lib().ldpc_fd_profile_read(int(kernel), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
