@@ -76,7 +76,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="gf64_n1000")
     ap.add_argument("--point", type=int, default=2, help="Eb/N0 index (gf64_n1000: 2 -> 2.5 dB)")
-    ap.add_argument("--prec", default="fp16", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--mode", default="fused", choices=["fused", "plain"])
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")

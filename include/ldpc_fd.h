@@ -131,12 +131,16 @@ int32_t ldpc_fd_decode(ldpc_fd_code code, int32_t frames, const float *llr, int3
  *   not NULL, the
  *   tentative decision of round l: hard[frames][N], fsynd[frames][M] (Fourier
  *   syndrome words, bit i = syndrome bit i+1 of the check) and synd[frames][M]
- *   (direct syndrome of hard).  All arrays are device memory; FP32 storage.
- *   mode selects which kernels compute it (PLAIN or FUSED).
- * Errors: E_INVALID, E_HIP. */
+ *   (direct syndrome of hard).  All arrays are device memory in the FP32 message
+ *   layout.  mode selects which kernels compute it (PLAIN or FUSED).  prec
+ *   selects the storage type the FUSED pass reads and writes: the imported
+ *   state is rounded to it first and the result widened back to FP32, so the
+ *   difference to an FP32 round is the one-round storage error (PLAIN: FP32
+ *   only).  The call allocates temporary device memory and synchronises.
+ * Errors: E_INVALID, E_UNSUPPORTED (PLAIN with prec != FP32), E_HIP. */
 int32_t ldpc_fd_round(ldpc_fd_code code, int32_t frames, const float *llr, const float *c2v_in,
                       float *v2c_out, float *c2v_out, uint8_t *hard, uint8_t *fsynd,
-                      uint8_t *synd, int32_t mode, void *stream);
+                      uint8_t *synd, int32_t mode, int32_t prec, void *stream);
 
 /* Kernel timing for measurement (calling thread only).  While enabled,
  * ldpc_fd_decode records a pair of HIP events on its stream around every launch

@@ -60,6 +60,8 @@ int32_t upload(ldpc_fd_code_s* c, const std::vector<T>& h, const T** out) {
 // Kernel geometry selection.  Rows of weight <= 8 use 16 entries per lane
 // (L = Q/16 lanes per frame); heavier rows (<= 16) use 4 entries per lane so
 // that the per-check stash of k messages stays in registers.
+constexpr long kMaxFusedBlocks = 2048;
+
 template <int LOGQ, int LOGR, int KMAX>
 struct Impl {
   using G = Geo<LOGQ, LOGR>;
@@ -82,14 +84,21 @@ struct Impl {
     hipLaunchKernelGGL((k_check_plain<G, KMAX>), dim3(blocks(items)), dim3(64 * kWaves), lds(), s, cd, F,
                        v2c, c2v, active);
   }
+  // Grid of the grid-stride fused pass: enough workgroups for the largest
+  // possible active list, capped, and a multiple of the XCD count.
+  static unsigned fused_blocks(const DevCode& cd, int Fmax) {
+    const long items = (long)((Fmax + G::T - 1) / G::T) * cd.M;
+    long b = std::min<long>(blocks(items), kMaxFusedBlocks);
+    b = (b + kXcds - 1) / kXcds * kXcds;
+    return (unsigned)std::max<long>(b, kXcds);
+  }
   template <typename S>
   static void fused(const DevCode& cd, int Fmax, const float* llr, const S* cin, S* cout, uint8_t* hard,
                     uint8_t* fsw, const int* alist, const int* nact, int first, int decide, int write,
                     hipStream_t s) {
-    const long items = (long)((Fmax + G::T - 1) / G::T) * cd.M;
-    if (items == 0) return;
-    hipLaunchKernelGGL((k_fused<G, KMAX, S>), dim3(blocks(items)), dim3(64 * kWaves), lds(), s, cd, llr,
-                       cin, cout, hard, fsw, alist, nact, first, decide, write);
+    if (Fmax == 0) return;
+    hipLaunchKernelGGL((k_fused<G, KMAX, S>), dim3(fused_blocks(cd, Fmax)), dim3(64 * kWaves), lds(), s, cd,
+                       llr, cin, cout, hard, fsw, alist, nact, first, decide, write);
   }
 };
 
@@ -187,6 +196,21 @@ int32_t read_count(const void* dptr, hipStream_t s, int* out) {
 }
 
 unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// Syndromes of the current decisions for the active frames (alist/nact, or all
+// F frames gated by `active`).
+void launch_syndrome(const ldpc_fd_code_s* c, int F, const uint8_t* hard, const uint8_t* fsw, uint8_t* synd,
+                     uint8_t* fsynd, uint32_t* unsat, uint32_t* mism, const int* alist, const int* nact,
+                     const uint32_t* active, hipStream_t s) {
+  const size_t lds = (size_t)c->N + c->E;
+  if (lds <= 65536) {
+    hipLaunchKernelGGL(k_syndrome_frames, dim3((unsigned)std::min(F, 4096)), dim3(256), lds, s, c->dev, hard, fsw,
+                       synd, fsynd, unsat, mism, alist, nact, F, active);
+  } else {
+    hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, c->dev, hard, fsw, synd,
+                       fsynd, unsat, mism, alist, nact, F, active);
+  }
+}
 
 // Per-thread kernel timing (ldpc_fd_profile_*).
 struct Profile {
@@ -302,7 +326,7 @@ int32_t ldpc_fd_create_code(int32_t M, int32_t N, int32_t m, const int32_t* row_
   auto* c = new (std::nothrow) ldpc_fd_code_s();
   if (!c) return fail(LDPC_FD_E_NOMEM, "host allocation failed");
   c->M = M; c->N = N; c->m = m; c->q = q; c->E = E; c->kmax = kmax; c->poly = poly;
-  hipGetDevice(&c->device);
+  (void)hipGetDevice(&c->device);
   DevCode& d = c->dev;
   d.M = M; d.N = N; d.E = E; d.m = m;
   int32_t rc;
@@ -375,9 +399,7 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
         timed(LDPC_FD_K_CHECK, s, [&] { I::check_plain(cd, F, w.v2c, w.c2v, w.active, s); });
         timed(LDPC_FD_K_VAR, s, [&] { I::var_plain(cd, F, llr, w.c2v, w.v2c, hard, w.fsw, w.active, 0, s); });
       });
-      hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, cd, hard, w.fsw, synd,
-                         (uint8_t*)nullptr, w.unsat, w.mism, (const int*)nullptr, (const int*)nullptr, F,
-                         w.active);
+      launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
       hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,
                          iters, status, w.count);
@@ -413,8 +435,7 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
   if (!run_pass(1, 0, 1, nullptr, w.buf[1])) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
   for (int ell = 1; ell <= max_iter; ++ell) {
     run_pass(0, 1, ell < max_iter, w.buf[ell & 1], w.buf[(ell + 1) & 1]);
-    hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, cd, hard, w.fsw, synd,
-                       (uint8_t*)nullptr, w.unsat, w.mism, w.alist, w.nact, F, (const uint32_t*)nullptr);
+    launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, w.alist, w.nact, nullptr, s);
     hipLaunchKernelGGL(k_retire_compact, dim3(1), dim3(1024), 0, s, ell, max_iter, w.alist, w.tmp, w.nact, w.unsat,
                        w.mism, iters, status);
     if (ell % chunk == 0 || ell == max_iter) {
@@ -428,7 +449,8 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
 }
 
 int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* c2v_in, float* v2c_out,
-                      float* c2v_out, uint8_t* hard, uint8_t* fsynd, uint8_t* synd, int32_t mode, void* stream) {
+                      float* c2v_out, uint8_t* hard, uint8_t* fsynd, uint8_t* synd, int32_t mode, int32_t prec,
+                      void* stream) {
   if (!c) return fail(LDPC_FD_E_INVALID, "code is NULL");
   if (F < 0) return fail(LDPC_FD_E_INVALID, "frames < 0");
   if (F == 0) return LDPC_FD_OK;
@@ -437,11 +459,17 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   if (mode == LDPC_FD_MODE_PLAIN && !v2c_out) return fail(LDPC_FD_E_INVALID, "PLAIN round needs v2c_out");
   if (mode == LDPC_FD_MODE_FUSED && v2c_out) return fail(LDPC_FD_E_INVALID, "FUSED round does not form v2c_out");
   if (mode != LDPC_FD_MODE_PLAIN && mode != LDPC_FD_MODE_FUSED) return fail(LDPC_FD_E_INVALID, "unknown mode");
+  if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
+  if (mode == LDPC_FD_MODE_PLAIN && prec != LDPC_FD_FP32) return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN is FP32 only");
   hipStream_t s = (hipStream_t)stream;
   const DevCode& cd = c->dev;
   char* tmp = nullptr;
   const size_t n_fsw = align256((size_t)F * c->E), n4 = align256((size_t)F * 4);
-  HIP_TRY(hipMalloc((void**)&tmp, n_fsw + 4 * n4 + 256));
+  const size_t n_msg = (size_t)F * c->E * c->q;
+  const size_t n_st = prec == LDPC_FD_FP32 ? 0 : align256(n_msg * 2);
+  HIP_TRY(hipMalloc((void**)&tmp, n_fsw + 4 * n4 + 256 + 2 * n_st));
+  char* st_in = tmp + n_fsw + 4 * n4 + 256;
+  char* st_out = st_in + n_st;
   uint8_t* fsw = (uint8_t*)tmp;
   uint32_t* active = (uint32_t*)(tmp + n_fsw);
   uint32_t* unsat = (uint32_t*)(tmp + n_fsw + n4);
@@ -455,16 +483,24 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
     using I = decltype(impl);
     if (mode == LDPC_FD_MODE_PLAIN) {
       I::var_plain(cd, F, llr, c2v_in, v2c_out, hard, fsw, nullptr, c2v_in ? 0 : 1, s);
-      if (c2v_in)
-        hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, cd, hard, fsw, synd, fsynd,
-                           unsat, mism, (const int*)nullptr, (const int*)nullptr, F, (const uint32_t*)nullptr);
+      if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
       I::check_plain(cd, F, v2c_out, c2v_out, nullptr, s);
-    } else {
+    } else if (prec == LDPC_FD_FP32) {
       I::template fused<float>(cd, F, llr, c2v_in, c2v_out, hard, fsw, alist, nact, c2v_in ? 0 : 1,
                                c2v_in ? 1 : 0, 1, s);
-      if (c2v_in)
-        hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, cd, hard, fsw, synd, fsynd,
-                           unsat, mism, alist, nact, F, (const uint32_t*)nullptr);
+      if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, alist, nact, nullptr, s);
+    } else {
+      // round the imported state to the storage type, run the pass on it, widen the result
+      auto run = [&](auto tag) {
+        using S = decltype(tag);
+        const unsigned g = (unsigned)std::min<size_t>((n_msg / 4 + 255) / 256, 65536);
+        if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, (S*)st_in, n_msg / 4);
+        I::template fused<S>(cd, F, llr, c2v_in ? (const S*)st_in : nullptr, (S*)st_out, hard, fsw, alist, nact,
+                             c2v_in ? 0 : 1, c2v_in ? 1 : 0, 1, s);
+        hipLaunchKernelGGL((k_convert<S, float>), dim3(g), dim3(256), 0, s, (const S*)st_out, c2v_out, n_msg / 4);
+      };
+      if (prec == LDPC_FD_FP16) run(_Float16{}); else run(bf16_t{});
+      if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, alist, nact, nullptr, s);
     }
   });
   hipError_t e1 = hipStreamSynchronize(s);

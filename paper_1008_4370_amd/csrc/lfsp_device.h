@@ -183,16 +183,24 @@ struct IO<float> {
     *reinterpret_cast<float4*>(p) = make_float4(i[0], i[1], i[2], i[3]);
   }
 };
+// FP16 words hold 512 * (-log2|P|): magnitudes up to 100 * 512 = 51200 stay
+// below the FP16 maximum, and the 11-bit relative precision reaches down to
+// -log2|P| = 2^-23 before subnormals.  Messages close to certainty (|P| = 1 -
+// delta, magnitude ~ delta / ln 2) carry the small symbol probabilities in
+// delta, which an unscaled FP16 word would flush into its subnormal range.
+constexpr float kHalfScale = 512.0f;
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 template <>
 struct IO<_Float16> {
   static __device__ __forceinline__ void load4(const _Float16* p, float* o) {
     const half4_t x = *reinterpret_cast<const half4_t*>(p);
-    o[0] = (float)x[0]; o[1] = (float)x[1]; o[2] = (float)x[2]; o[3] = (float)x[3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = (float)x[i] * (1.0f / kHalfScale);
   }
   static __device__ __forceinline__ void store4(_Float16* p, const float* i) {
     half4_t x;
-    x[0] = (_Float16)i[0]; x[1] = (_Float16)i[1]; x[2] = (_Float16)i[2]; x[3] = (_Float16)i[3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = (_Float16)(i[k] * kHalfScale);
     *reinterpret_cast<half4_t*>(p) = x;
   }
 };

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_check_plain(DevCode cd, int F, const fl
 }
 
 // ---------------------------------------------------------------------------
-// FUSED decoder: one pass per round.  One wave = (group of T active frames,
+// FUSED decoder: one pass per round.  Work item = (group of T active frames,
 // check).  For each edge (c, v) the pass rebuilds Lambda_vc = L0 [+] L_c'v from
 // the stored state of round l, runs the check node and writes round l+1.  On
 // the owner visit of v (the edge with the smaller index) it also forms the
@@ -217,23 +217,11 @@ __global__ __launch_bounds__(256) void k_check_plain(DevCode cd, int F, const fl
 //   decide:  form the decision of round l.
 //   write:   store round l+1 (off in the last pass).
 template <class G, int KMAX, typename S>
-__global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restrict__ llr,
-                                               const S* __restrict__ cin, S* __restrict__ cout,
-                                               uint8_t* __restrict__ hard, uint8_t* __restrict__ fsw,
-                                               const int* __restrict__ alist, const int* __restrict__ nact_p,
-                                               int first, int decide_flag, int write) {
-  extern __shared__ float lds[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long item = (long)blockIdx.x * (blockDim.x >> 6) + wave;
-  const int nact = *nact_p;
-  const int groups = (nact + G::T - 1) / G::T;
-  if (item >= (long)groups * cd.M) return;
-  const int g = (int)(item / cd.M), c = (int)(item % cd.M);
-  const int fl = lane / G::L, zl = lane % G::L;
-  const int slot = g * G::T + fl;
-  const bool valid = slot < nact;
-  const int f = alist[valid ? slot : nact - 1];
-  float* row = lds + (wave * G::T + fl) * G::QP;
+__device__ __forceinline__ void fused_item(const DevCode& cd, const float* __restrict__ llr,
+                                           const S* __restrict__ cin, S* __restrict__ cout,
+                                           uint8_t* __restrict__ hard, uint8_t* __restrict__ fsw, int f,
+                                           bool valid, int c, float* row, int zl, int first, int decide_flag,
+                                           int write) {
   const int e0 = uni(cd.row_ptr[c]), deg = uni(cd.row_ptr[c + 1]) - e0;
   const size_t fb = (size_t)f * cd.E * G::Q;
   float st[KMAX][G::R];
@@ -250,14 +238,13 @@ __global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restri
       const int h = uni(cd.e_label[e]);
       float t[G::LOGQ];
       prior_coeffs<G>(llr + ((size_t)f * cd.N + v) * G::LOGQ, t);
-      float* Y = st[j];
       if (first) {
 #pragma unroll
-        for (int r = 0; r < G::R; ++r) Y[r] = (r == 0 && zl == 0) ? 1.0f : 0.0f;
+        for (int r = 0; r < G::R; ++r) st[j][r] = (r == 0 && zl == 0) ? 1.0f : 0.0f;
       } else {
         load_msg<G, S>(cin + fb + (size_t)eo * G::Q, zl, st[j]);
 #pragma unroll
-        for (int r = 0; r < G::R; ++r) Y[r] = gamma_inv(Y[r]);
+        for (int r = 0; r < G::R; ++r) st[j][r] = gamma_inv(st[j][r]);
       }
       conv_prior<G>(st[j], t);
       if (decide_flag && e < eo) {
@@ -301,6 +288,86 @@ __global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restri
   }
 }
 
+// Number of XCDs; workgroups are dispatched to them round-robin.
+constexpr int kXcds = 8;
+
+// Grid-stride pass over the active frames.  Frame group g is handled by the
+// workgroups of XCD g % 8, so both reads of a message within a pass (as the
+// other edge of its variable, and by its own check at the owner visit) come
+// from the same XCD's L2.  gridDim.x must be a multiple of 8.
+template <class G, int KMAX, typename S>
+__global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restrict__ llr,
+                                               const S* __restrict__ cin, S* __restrict__ cout,
+                                               uint8_t* __restrict__ hard, uint8_t* __restrict__ fsw,
+                                               const int* __restrict__ alist, const int* __restrict__ nact_p,
+                                               int first, int decide_flag, int write) {
+  extern __shared__ float lds[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int waves = blockDim.x >> 6;
+  const int nact = *nact_p;
+  const int groups = (nact + G::T - 1) / G::T;
+  const int xcd = blockIdx.x % kXcds;
+  const long stride = (long)(gridDim.x / kXcds) * waves;
+  const long groups_x = (groups - xcd + kXcds - 1) / kXcds;
+  const long items = groups_x * cd.M;
+  const int fl = lane / G::L, zl = lane % G::L;
+  float* row = lds + (wave * G::T + fl) * G::QP;
+  for (long it = (long)(blockIdx.x / kXcds) * waves + wave; it < items; it += stride) {
+    const int g = xcd + kXcds * (int)(it / cd.M);
+    const int c = (int)(it % cd.M);
+    const int slot = g * G::T + fl;
+    const bool valid = slot < nact;
+    const int f = alist[valid ? slot : nact - 1];
+    fused_item<G, KMAX, S>(cd, llr, cin, cout, hard, fsw, f, valid, c, row, zl, first, decide_flag, write);
+  }
+}
+
+// Syndromes of the tentative decision, one workgroup per active frame: the
+// frame's hard decisions and per-edge Fourier sign words are staged in LDS
+// (coalesced), then each thread forms checks c = tid, tid + 256, ...:
+// direct s_c = sum_{v in V_c} h_cv x^_v and the Fourier word = XOR of the
+// check's edge words (edges of a check are contiguous).  unsat[f] / mism[f]
+// are set to whether any check is nonzero / any pair differs.
+__global__ __launch_bounds__(256) void k_syndrome_frames(DevCode cd, const uint8_t* __restrict__ hard,
+                                                         const uint8_t* __restrict__ fsw,
+                                                         uint8_t* __restrict__ synd, uint8_t* __restrict__ fsynd,
+                                                         uint32_t* __restrict__ unsat, uint32_t* __restrict__ mism,
+                                                         const int* __restrict__ alist,
+                                                         const int* __restrict__ nact_p, int F_all,
+                                                         const uint32_t* __restrict__ active) {
+  extern __shared__ uint8_t sm[];
+  uint8_t* sh = sm;            // [N]
+  uint8_t* sw = sm + cd.N;     // [E]
+  const int nact = nact_p ? *nact_p : F_all;
+  for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
+    const int f = alist ? alist[slot] : slot;
+    if (active && !active[f]) continue;  // uniform over the block
+    for (int i = threadIdx.x; i < cd.N; i += blockDim.x) sh[i] = hard[(size_t)f * cd.N + i];
+    for (int i = threadIdx.x; i < cd.E; i += blockDim.x) sw[i] = fsw[(size_t)f * cd.E + i];
+    __syncthreads();
+    int bad = 0, mm = 0;
+    for (int c = threadIdx.x; c < cd.M; c += blockDim.x) {
+      const int e0 = cd.row_ptr[c], e1 = cd.row_ptr[c + 1];
+      int s = 0, sf = 0;
+      for (int e = e0; e < e1; ++e) {
+        const int x = sh[cd.e_var[e]];
+        if (x) s ^= cd.gexp[cd.glog[cd.e_label[e]] + cd.glog[x]];
+        sf ^= sw[e];
+      }
+      synd[(size_t)f * cd.M + c] = (uint8_t)s;
+      if (fsynd) fsynd[(size_t)f * cd.M + c] = (uint8_t)sf;
+      bad |= s | sf;
+      mm |= s != sf;
+    }
+    bad = __syncthreads_or(bad);
+    mm = __syncthreads_or(mm);
+    if (threadIdx.x == 0) {
+      unsat[f] = bad ? 1u : 0u;
+      mism[f] = mm ? 1u : 0u;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Syndromes of the tentative decision (one thread per (active frame, check)):
 // direct s_c = sum_{v in V_c} h_cv x^_v and Fourier word = XOR of per-edge
@@ -329,6 +396,16 @@ __global__ void k_syndrome(DevCode cd, const uint8_t* __restrict__ hard, const u
   if (fsynd) fsynd[(size_t)f * cd.M + c] = (uint8_t)sf;
   if (s | sf) atomicOr(&unsat[f], 1u);
   if (s != sf) atomicOr(&mism[f], 1u);
+}
+
+// Elementwise conversion between message storage types (n4 groups of 4).
+template <typename Sin, typename Sout>
+__global__ void k_convert(const Sin* __restrict__ in, Sout* __restrict__ out, size_t n4) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
+    float v[4];
+    IO<Sin>::load4(in + 4 * i, v);
+    IO<Sout>::store4(out + 4 * i, v);
+  }
 }
 
 __global__ void k_init_frames(int F, uint32_t* active, uint32_t* unsat, uint32_t* mism, int* alist,

@@ -33,7 +33,7 @@ _SIGS = {
     "ldpc_fd_decode": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _i32, _i32, _c_void_p, _c_void_p, _c_void_p,
                               _c_void_p, _c_void_p, _i64, _c_void_p]),
     "ldpc_fd_round": (_i32, [_c_void_p, _i32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
-                             _c_void_p, _i32, _c_void_p]),
+                             _c_void_p, _i32, _i32, _c_void_p]),
     "ldpc_fd_profile_enable": (_i32, [_i32]),
     "ldpc_fd_profile_read": (_i32, [_i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
     "ldpc_fd_last_error": (ctypes.c_char_p, []),
@@ -152,7 +152,7 @@ def decode(code: Code, llr, max_iter: int, prec: str = "fp32", mode: str = "fuse
     return Decoder(code, llr.shape[0], prec, mode, device=llr.device)(llr, max_iter)
 
 
-def round_step(code: Code, llr, c2v_in=None, mode: str = "plain"):
+def round_step(code: Code, llr, c2v_in=None, mode: str = "plain", prec: str = "fp32"):
     """One flooding round from an imported FP32 state (ldpc_fd_round)."""
     import torch
     F = llr.shape[0]
@@ -163,7 +163,7 @@ def round_step(code: Code, llr, c2v_in=None, mode: str = "plain"):
     fsynd = torch.zeros((F, code.M), dtype=torch.uint8, device=dev)
     synd = torch.zeros((F, code.M), dtype=torch.uint8, device=dev)
     _check(lib().ldpc_fd_round(code.handle, F, _ptr(llr), _ptr(c2v_in), _ptr(v2c_out), _ptr(c2v_out),
-                               _ptr(hard), _ptr(fsynd), _ptr(synd), MODE[mode], _stream()))
+                               _ptr(hard), _ptr(fsynd), _ptr(synd), MODE[mode], PREC[prec], _stream()))
     return dict(c2v=c2v_out, v2c=v2c_out, hard=hard, fsynd=fsynd, synd=synd)
 
 

@@ -46,3 +46,17 @@ def fsynd_near_tie(tc, post: np.ndarray) -> np.ndarray:
         vals = Q[:, tc.edge_var[e], tc.fsyn_pts[e]]
         mask[:, tc.edge_check[e]] |= (np.abs(vals) < TAU).any(-1)
     return mask
+
+
+def round_storage(w: np.ndarray, prec: str) -> np.ndarray:
+    """Round FP32 state words to the decoder's 16-bit storage and back: FP16 words
+    hold 512 * word (round to nearest even), BF16 words the top 16 bits of the
+    FP32 word (round to nearest even)."""
+    w = np.asarray(w, dtype=np.float32)
+    if prec == "fp32":
+        return w
+    if prec == "fp16":
+        return (w * np.float32(512)).astype(np.float16).astype(np.float32) / np.float32(512)
+    u = w.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
