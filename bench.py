@@ -81,7 +81,27 @@ def main():
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames-per-worker", type=int, default=2)
+    ap.add_argument("--lane-entries", type=int, default=0, help="kernel variant (4/8/16; 0 = library default)")
+    ap.add_argument("--grid-blocks", type=int, default=0, help="fused-pass grid (0 = library default)")
+    ap.add_argument("--chunk", type=int, default=0, help="rounds between host checks (0 = default)")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="time steps without per-kernel HIP events (lets the decoder replay graphs); "
+                         "roofline is then omitted")
+    ap.add_argument("--graphs", type=int, default=-1, help="1/0: replay captured round chunks (-1 = default)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (calibrates rocprofv3 "
+                         "FETCH_SIZE/WRITE_SIZE against a known byte count) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "frames would shard across GPUs with no per-round exchange (see DESIGN.md).", file=sys.stderr)
@@ -99,6 +119,12 @@ def main():
     import torch
     from paper_1008_4370_amd import decoder as D
     code = D.Code.from_synth(batch.code)
+    tune = {k: v for k, v in (("lane_entries", args.lane_entries), ("grid_blocks", args.grid_blocks),
+                              ("chunk", args.chunk)) if v}
+    if args.graphs >= 0:
+        tune["graphs"] = args.graphs
+    if tune:
+        code.set_tuning(**tune)
     dec = D.Decoder(code, F, args.prec, args.mode)
     llr = torch.from_numpy(batch.llr).cuda()
     for _ in range(args.warmup):
@@ -106,7 +132,7 @@ def main():
     torch.cuda.synchronize()
     kernel = D.K_FUSED if args.mode == "fused" else D.K_CHECK
     D.profile_read(D.K_FUSED), D.profile_read(D.K_CHECK), D.profile_read(D.K_VAR)
-    D.profile_enable(True)
+    D.profile_enable(not args.no_kernel_timing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -126,7 +152,9 @@ def main():
     frame_err = np.any(hard != batch.cw, axis=1)
     bit_err = int(np.sum((((hard.astype(np.int64) ^ batch.cw)[..., None] >> np.arange(batch.code.m)) & 1)))
     s = 4 if args.prec == "fp32" else 2
-    if args.mode == "fused":
+    if kms <= 0:
+        achieved, roof_kernel = None, None
+    elif args.mode == "fused":
         total_bytes = alg_bytes(batch.code, iters, s) * args.steps
         achieved = total_bytes / (kms / 1e3) / 1e9
         roof_kernel = "k_fused"
@@ -158,8 +186,9 @@ def main():
             "frames": F,
             "info_bits_per_frame": info_bits,
             "parallelism": "1 GPU",
+            "tuning": code.get_tuning(),
         },
-        "roofline": {
+        "roofline": None if achieved is None else {
             "bound": "hbm",
             "kernel": roof_kernel,
             "achieved": round(achieved, 1),

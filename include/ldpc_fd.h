@@ -142,6 +142,24 @@ int32_t ldpc_fd_round(ldpc_fd_code code, int32_t frames, const float *llr, const
                       float *v2c_out, float *c2v_out, uint8_t *hard, uint8_t *fsynd,
                       uint8_t *synd, int32_t mode, int32_t prec, void *stream);
 
+/* Tuning of a code object's kernels (results are identical for every setting;
+ * only speed changes).  Set by the autotuner, read back for its cache.
+ *   LDPC_FD_TUNE_LANE_ENTRIES: entries of a frame's 2^m-vector held per lane
+ *     (4, 8 or 16; 16 needs m <= 7, rows of weight > 8 use 4).  Fewer entries
+ *     per lane means more lanes per frame, fewer registers and more waves.
+ *   LDPC_FD_TUNE_GRID_BLOCKS: workgroups of the grid-stride fused pass (>= 8).
+ *   LDPC_FD_TUNE_CHUNK: rounds between host reads of the active-frame count.
+ *   LDPC_FD_TUNE_GRAPHS: 1 (default) = the FUSED decoder captures a chunk of
+ *     rounds into a HIP graph once per (frames, buffers, settings) and replays
+ *     it; 0 = launch every kernel from the host.  Replayed chunks round the
+ *     chunk up to an even number of rounds.  While kernel timing is enabled
+ *     (ldpc_fd_profile_enable) kernels are launched from the host.
+ * Errors: E_INVALID (unknown key or value), E_UNSUPPORTED (no such variant). */
+enum { LDPC_FD_TUNE_LANE_ENTRIES = 0, LDPC_FD_TUNE_GRID_BLOCKS = 1, LDPC_FD_TUNE_CHUNK = 2,
+       LDPC_FD_TUNE_GRAPHS = 3 };
+int32_t ldpc_fd_set_tuning(ldpc_fd_code code, int32_t key, int32_t value);
+int32_t ldpc_fd_get_tuning(ldpc_fd_code code, int32_t key, int32_t *value);
+
 /* Kernel timing for measurement (calling thread only).  While enabled,
  * ldpc_fd_decode records a pair of HIP events on its stream around every launch
  * of the per-round kernels: LDPC_FD_K_FUSED (the fused pass), LDPC_FD_K_CHECK

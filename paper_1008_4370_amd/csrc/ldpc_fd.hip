@@ -4,6 +4,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -34,10 +35,37 @@ const uint32_t kDefaultPoly[9] = {0, 0x3, 0x7, 0xB, 0x13, 0x25, 0x43, 0x89, 0x11
 struct ldpc_fd_code_s {
   int M = 0, N = 0, m = 0, q = 0, E = 0, kmax = 0;
   uint32_t poly = 0;
+  // tuning (ldpc_fd_set_tuning): log2 entries per lane, fused grid cap, rounds per
+  // host check, replay of captured round chunks
+  int logr = 4, blocks = 2048, chunk = 4, graphs = 1;
   int device = 0;
   std::vector<void*> allocs;
   DevCode dev{};
+  // Captured chunks of rounds of the fused decoder, keyed by everything their
+  // kernel arguments depend on.
+  struct GraphKey {
+    int F, prec, chunk, max_iter, logr, blocks, prof;
+    const void *ws, *llr, *hard, *synd, *iters, *status;
+    bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
+  };
+  struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+    std::vector<hipEvent_t> ev;  // per-round fused-pass start/stop events (profiling)
+  };
+  std::vector<GraphEntry> gcache;
+  hipStream_t cap_stream = nullptr;
+  std::mutex gmu;  // guards gcache and cap_stream
+  void drop_graphs() {
+    for (auto& g : gcache) {
+      (void)hipGraphExecDestroy(g.exec);
+      for (auto e : g.ev) (void)hipEventDestroy(e);
+    }
+    gcache.clear();
+  }
   ~ldpc_fd_code_s() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocs) (void)hipFree(p);
   }
 };
@@ -60,8 +88,6 @@ int32_t upload(ldpc_fd_code_s* c, const std::vector<T>& h, const T** out) {
 // Kernel geometry selection.  Rows of weight <= 8 use 16 entries per lane
 // (L = Q/16 lanes per frame); heavier rows (<= 16) use 4 entries per lane so
 // that the per-check stash of k messages stays in registers.
-constexpr long kMaxFusedBlocks = 2048;
-
 template <int LOGQ, int LOGR, int KMAX>
 struct Impl {
   using G = Geo<LOGQ, LOGR>;
@@ -86,27 +112,35 @@ struct Impl {
   }
   // Grid of the grid-stride fused pass: enough workgroups for the largest
   // possible active list, capped, and a multiple of the XCD count.
-  static unsigned fused_blocks(const DevCode& cd, int Fmax) {
+  static unsigned fused_blocks(const DevCode& cd, int Fmax, int cap) {
     const long items = (long)((Fmax + G::T - 1) / G::T) * cd.M;
-    long b = std::min<long>(blocks(items), kMaxFusedBlocks);
+    long b = std::min<long>(blocks(items), cap);
     b = (b + kXcds - 1) / kXcds * kXcds;
     return (unsigned)std::max<long>(b, kXcds);
   }
   template <typename S>
-  static void fused(const DevCode& cd, int Fmax, const float* llr, const S* cin, S* cout, uint8_t* hard,
+  static void fused(const DevCode& cd, int Fmax, const float* prior, const S* cin, S* cout, uint8_t* hard,
                     uint8_t* fsw, const int* alist, const int* nact, int first, int decide, int write,
-                    hipStream_t s) {
+                    int cap, hipStream_t s, const int* ell_p = nullptr, int max_iter = 0) {
     if (Fmax == 0) return;
-    hipLaunchKernelGGL((k_fused<G, KMAX, S>), dim3(fused_blocks(cd, Fmax)), dim3(64 * kWaves), lds(), s, cd,
-                       llr, cin, cout, hard, fsw, alist, nact, first, decide, write);
+    hipLaunchKernelGGL((k_fused<G, KMAX, S>), dim3(fused_blocks(cd, Fmax, cap)), dim3(64 * kWaves), lds(), s, cd,
+                       prior, cin, cout, hard, fsw, alist, nact, first, decide, write, ell_p, max_iter);
   }
 };
 
+// Kernel variant: rows of weight <= 8 have variants with 4, 8 or 16 entries
+// per lane (log2 R = 2, 3, 4; 16 entries only for q <= 128, where the kernel
+// keeps its stash in registers); rows of weight 9..16 use 4 entries per lane.
 template <int LOGQ, class Fn>
-bool dispatch_q(int kmax, Fn&& fn) {
-  constexpr int LOGR_SMALLK = LOGQ < 4 ? LOGQ : 4;
+bool dispatch_q(int kmax, int logr, Fn&& fn) {
   if (kmax <= 8) {
-    fn(Impl<LOGQ, LOGR_SMALLK, 8>{});
+    if constexpr (LOGQ >= 4 && LOGQ <= 7) {
+      if (logr == 4) { fn(Impl<LOGQ, 4, 8>{}); return true; }
+    }
+    if constexpr (LOGQ >= 3) {
+      if (logr == 3) { fn(Impl<LOGQ, 3, 8>{}); return true; }
+    }
+    fn(Impl<LOGQ, 2, 8>{});
     return true;
   }
   if (kmax <= 16) {
@@ -117,15 +151,15 @@ bool dispatch_q(int kmax, Fn&& fn) {
 }
 
 template <class Fn>
-bool dispatch(int m, int kmax, Fn&& fn) {
+bool dispatch(int m, int kmax, int logr, Fn&& fn) {
   switch (m) {
-    case 2: return dispatch_q<2>(kmax, fn);
-    case 3: return dispatch_q<3>(kmax, fn);
-    case 4: return dispatch_q<4>(kmax, fn);
-    case 5: return dispatch_q<5>(kmax, fn);
-    case 6: return dispatch_q<6>(kmax, fn);
-    case 7: return dispatch_q<7>(kmax, fn);
-    case 8: return dispatch_q<8>(kmax, fn);
+    case 2: return dispatch_q<2>(kmax, logr, fn);
+    case 3: return dispatch_q<3>(kmax, logr, fn);
+    case 4: return dispatch_q<4>(kmax, logr, fn);
+    case 5: return dispatch_q<5>(kmax, logr, fn);
+    case 6: return dispatch_q<6>(kmax, logr, fn);
+    case 7: return dispatch_q<7>(kmax, logr, fn);
+    case 8: return dispatch_q<8>(kmax, logr, fn);
     default: return false;
   }
 }
@@ -145,6 +179,7 @@ struct PlainWs {
   uint32_t* count;
 };
 struct FusedWs {
+  float* prior;  // [F][N][m] tanh(L/2)
   void* buf[2];
   uint8_t* fsw;
   int* alist;
@@ -152,6 +187,7 @@ struct FusedWs {
   uint32_t* unsat;
   uint32_t* mism;
   int* nact;
+  int* ell;
 };
 
 size_t plain_layout(const ldpc_fd_code_s* c, int F, char* base, PlainWs* w) {
@@ -173,6 +209,7 @@ size_t fused_layout(const ldpc_fd_code_s* c, int F, int prec, char* base, FusedW
   const size_t msg = align256((size_t)F * c->E * c->q * msg_bytes(prec));
   size_t off = 0;
   auto take = [&](size_t n) { char* p = base ? base + off : nullptr; off += align256(n); return p; };
+  char* pt = take((size_t)F * c->N * c->m * 4);
   char* b0 = take(msg);
   char* b1 = take(msg);
   char* p2 = take((size_t)F * c->E);
@@ -181,7 +218,9 @@ size_t fused_layout(const ldpc_fd_code_s* c, int F, int prec, char* base, FusedW
   char* p5 = take((size_t)F * 4);
   char* p6 = take((size_t)F * 4);
   char* p7 = take(4);
-  if (w) *w = FusedWs{{b0, b1}, (uint8_t*)p2, (int*)p3, (int*)p4, (uint32_t*)p5, (uint32_t*)p6, (int*)p7};
+  char* p8 = take(4);
+  if (w)
+    *w = FusedWs{(float*)pt, {b0, b1}, (uint8_t*)p2, (int*)p3, (int*)p4, (uint32_t*)p5, (uint32_t*)p6, (int*)p7, (int*)p8};
   return off;
 }
 
@@ -197,13 +236,20 @@ int32_t read_count(const void* dptr, hipStream_t s, int* out) {
 
 unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
+// Prior factors tanh(L/2) of every frame, symbol and bit.
+void launch_prior(const ldpc_fd_code_s* c, int F, const float* llr, float* prior, hipStream_t s) {
+  const size_t n = (size_t)F * c->N * c->m;
+  hipLaunchKernelGGL(k_prior_factors, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, llr,
+                     prior, n);
+}
+
 // Syndromes of the current decisions for the active frames (alist/nact, or all
 // F frames gated by `active`).
 void launch_syndrome(const ldpc_fd_code_s* c, int F, const uint8_t* hard, const uint8_t* fsw, uint8_t* synd,
                      uint8_t* fsynd, uint32_t* unsat, uint32_t* mism, const int* alist, const int* nact,
                      const uint32_t* active, hipStream_t s) {
-  const size_t lds = (size_t)c->N + c->E;
-  if (lds <= 65536) {
+  const size_t lds = 4 * (size_t)(((c->N + 3) >> 2) + ((c->E + 3) >> 2));
+  if (lds <= 60000) {
     hipLaunchKernelGGL(k_syndrome_frames, dim3((unsigned)std::min(F, 4096)), dim3(256), lds, s, c->dev, hard, fsw,
                        synd, fsynd, unsat, mism, alist, nact, F, active);
   } else {
@@ -257,6 +303,7 @@ int32_t ldpc_fd_create_code(int32_t M, int32_t N, int32_t m, const int32_t* row_
   *out = nullptr;
   if (m < 2 || m > 8) return fail(LDPC_FD_E_UNSUPPORTED, "m must be in 2..8");
   if (M < 1 || N < 1 || !row_ptr || !col || !val) return fail(LDPC_FD_E_INVALID, "bad shape or NULL array");
+  if (N >= (1 << 24)) return fail(LDPC_FD_E_UNSUPPORTED, "N must be below 2^24");
   const int q = 1 << m;
   if (row_ptr[0] != 0) return fail(LDPC_FD_E_INVALID, "row_ptr[0] != 0");
   for (int c = 0; c < M; ++c)
@@ -316,7 +363,11 @@ int32_t ldpc_fd_create_code(int32_t M, int32_t N, int32_t m, const int32_t* row_
   // graph tables
   std::vector<int> rp(row_ptr, row_ptr + M + 1), ev(col, col + E), eo(E, -1), ve(2 * N, -1);
   std::vector<uint8_t> el(E);
-  for (int e = 0; e < E; ++e) el[e] = (uint8_t)val[e];
+  std::vector<uint32_t> epk(E);
+  for (int e = 0; e < E; ++e) {
+    el[e] = (uint8_t)val[e];
+    epk[e] = (uint32_t)col[e] | ((uint32_t)val[e] << 24);
+  }
   std::vector<int> fill(N, 0);
   for (int e = 0; e < E; ++e) ve[2 * col[e] + fill[col[e]]++] = e;  // ascending e per variable
   for (int v = 0; v < N; ++v) {
@@ -326,13 +377,15 @@ int32_t ldpc_fd_create_code(int32_t M, int32_t N, int32_t m, const int32_t* row_
   auto* c = new (std::nothrow) ldpc_fd_code_s();
   if (!c) return fail(LDPC_FD_E_NOMEM, "host allocation failed");
   c->M = M; c->N = N; c->m = m; c->q = q; c->E = E; c->kmax = kmax; c->poly = poly;
+  c->logr = kmax > 8 ? 2 : m <= 3 ? m : m <= 7 ? 4 : 3;
   (void)hipGetDevice(&c->device);
   DevCode& d = c->dev;
   d.M = M; d.N = N; d.E = E; d.m = m;
   int32_t rc;
   if ((rc = upload(c, rp, &d.row_ptr)) || (rc = upload(c, ev, &d.e_var)) || (rc = upload(c, eo, &d.e_other)) ||
       (rc = upload(c, el, &d.e_label)) || (rc = upload(c, ve, &d.v_edges)) || (rc = upload(c, colsT, &d.colsT)) ||
-      (rc = upload(c, ginv, &d.ginv)) || (rc = upload(c, gexp, &d.gexp)) || (rc = upload(c, glog, &d.glog))) {
+      (rc = upload(c, ginv, &d.ginv)) || (rc = upload(c, gexp, &d.gexp)) || (rc = upload(c, glog, &d.glog)) ||
+      (rc = upload(c, epk, &d.e_pack))) {
     delete c;
     return rc;
   }
@@ -387,14 +440,14 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
     PlainWs w;
     plain_layout(c, F, (char*)workspace, &w);
     hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, w.active, w.unsat, w.mism, (int*)nullptr,
-                       (int*)nullptr, iters, status);
-    bool ok = dispatch(c->m, c->kmax, [&](auto impl) {
+                       (int*)nullptr, iters, status, (int*)nullptr);
+    bool ok = dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
       using I = decltype(impl);
       timed(LDPC_FD_K_VAR, s, [&] { I::var_plain(cd, F, llr, nullptr, w.v2c, hard, w.fsw, w.active, 1, s); });
     });
     if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
     for (int ell = 1; ell <= max_iter; ++ell) {
-      dispatch(c->m, c->kmax, [&](auto impl) {
+      dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
         using I = decltype(impl);
         timed(LDPC_FD_K_CHECK, s, [&] { I::check_plain(cd, F, w.v2c, w.c2v, w.active, s); });
         timed(LDPC_FD_K_VAR, s, [&] { I::var_plain(cd, F, llr, w.c2v, w.v2c, hard, w.fsw, w.active, 0, s); });
@@ -414,35 +467,84 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
   FusedWs w;
   fused_layout(c, F, prec, (char*)workspace, &w);
   hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, (uint32_t*)nullptr, w.unsat, w.mism, w.alist,
-                     w.nact, iters, status);
-  const int chunk = 4;
-  auto run_pass = [&](int first, int decide, int write, const void* cin, void* cout) {
-    return dispatch(c->m, c->kmax, [&](auto impl) {
+                     w.nact, iters, status, w.ell);
+  launch_prior(c, F, llr, w.prior, s);
+  auto run_pass = [&](int first, int decide, int write, const void* cin, void* cout, hipStream_t st) {
+    return dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
       using I = decltype(impl);
-      timed(LDPC_FD_K_FUSED, s, [&] {
       if (prec == LDPC_FD_FP32)
-        I::template fused<float>(cd, F, llr, (const float*)cin, (float*)cout, hard, w.fsw, w.alist, w.nact, first,
-                                 decide, write, s);
+        I::template fused<float>(cd, F, w.prior, (const float*)cin, (float*)cout, hard, w.fsw, w.alist, w.nact, first,
+                                 decide, write, c->blocks, st, w.ell, max_iter);
       else if (prec == LDPC_FD_FP16)
-        I::template fused<_Float16>(cd, F, llr, (const _Float16*)cin, (_Float16*)cout, hard, w.fsw, w.alist,
-                                    w.nact, first, decide, write, s);
+        I::template fused<_Float16>(cd, F, w.prior, (const _Float16*)cin, (_Float16*)cout, hard, w.fsw, w.alist,
+                                    w.nact, first, decide, write, c->blocks, st, w.ell, max_iter);
       else
-        I::template fused<bf16_t>(cd, F, llr, (const bf16_t*)cin, (bf16_t*)cout, hard, w.fsw, w.alist, w.nact,
-                                  first, decide, write, s);
-      });
+        I::template fused<bf16_t>(cd, F, w.prior, (const bf16_t*)cin, (bf16_t*)cout, hard, w.fsw, w.alist, w.nact,
+                                  first, decide, write, c->blocks, st, w.ell, max_iter);
     });
   };
-  if (!run_pass(1, 0, 1, nullptr, w.buf[1])) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
-  for (int ell = 1; ell <= max_iter; ++ell) {
-    run_pass(0, 1, ell < max_iter, w.buf[ell & 1], w.buf[(ell + 1) & 1]);
-    launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, w.alist, w.nact, nullptr, s);
-    hipLaunchKernelGGL(k_retire_compact, dim3(1), dim3(1024), 0, s, ell, max_iter, w.alist, w.tmp, w.nact, w.unsat,
-                       w.mism, iters, status);
-    if (ell % chunk == 0 || ell == max_iter) {
-      int left = 0;
-      if ((rc = read_count(w.nact, s, &left))) return rc;
-      if (left == 0) break;
+  // One round l (l read from device memory): fused pass l -> l+1 with the
+  // decision of round l, syndromes, stopping rule and compaction.
+  auto enqueue_round = [&](int ell_parity, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (e0) (void)hipEventRecord(e0, st);
+    run_pass(0, 1, -1, w.buf[ell_parity & 1], w.buf[(ell_parity + 1) & 1], st);
+    if (e1) (void)hipEventRecord(e1, st);
+    launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, w.alist, w.nact, nullptr, st);
+    hipLaunchKernelGGL(k_retire_compact, dim3(1), dim3(1024), 0, st, 0, max_iter, w.alist, w.tmp, w.nact, w.unsat,
+                       w.mism, iters, status, w.ell);
+  };
+  bool ok = true;
+  timed(LDPC_FD_K_FUSED, s, [&] { ok = run_pass(1, 0, 1, nullptr, w.buf[1], s); });
+  if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+  // Kernel timing needs per-launch events, which HIP cannot time inside a
+  // replayed graph: profiled decodes launch every round from the host.
+  if (!c->graphs || t_prof.on) {
+    for (int ell = 1; ell <= max_iter; ++ell) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (t_prof.on) {
+        e0 = t_prof.get();
+        e1 = t_prof.get();
+        if (e0 && e1) t_prof.ev[LDPC_FD_K_FUSED].emplace_back(e0, e1);
+      }
+      enqueue_round(ell, s, e0, e1);
+      if (ell % c->chunk == 0 || ell == max_iter) {
+        int left = 0;
+        if ((rc = read_count(w.nact, s, &left))) return rc;
+        if (left == 0) break;
+      }
     }
+    HIP_TRY(hipGetLastError());
+    return LDPC_FD_OK;
+  }
+  // Replay captured chunks of `chunk` rounds (even, so that chunk k always
+  // starts on the same ping-pong buffer).  Rounds past max_iter in the last
+  // chunk find no active frame and do nothing.
+  const int chunk = (c->chunk + 1) & ~1;
+  ldpc_fd_code_s::GraphKey key{F, prec, chunk, max_iter, c->logr, c->blocks, 0,
+                               workspace, llr, hard, synd, iters, status};
+  std::lock_guard<std::mutex> lock(c->gmu);
+  ldpc_fd_code_s::GraphEntry* ge = nullptr;
+  for (auto& g : c->gcache)
+    if (g.key == key) ge = &g;
+  if (!ge) {
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (c->gcache.size() >= 8) c->drop_graphs();
+    ldpc_fd_code_s::GraphEntry g{key, nullptr, {}};
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < chunk; ++r) enqueue_round(1 + r, c->cap_stream, nullptr, nullptr);
+    HIP_TRY(hipStreamEndCapture(c->cap_stream, &graph));
+    hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(LDPC_FD_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    c->gcache.push_back(g);
+    ge = &c->gcache.back();
+  }
+  for (int ell0 = 1; ell0 <= max_iter; ell0 += chunk) {
+    HIP_TRY(hipGraphLaunch(ge->exec, s));
+    int left = 0;
+    if ((rc = read_count(w.nact, s, &left))) return rc;
+    if (left == 0) break;
   }
   HIP_TRY(hipGetLastError());
   return LDPC_FD_OK;
@@ -467,9 +569,11 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   const size_t n_fsw = align256((size_t)F * c->E), n4 = align256((size_t)F * 4);
   const size_t n_msg = (size_t)F * c->E * c->q;
   const size_t n_st = prec == LDPC_FD_FP32 ? 0 : align256(n_msg * 2);
-  HIP_TRY(hipMalloc((void**)&tmp, n_fsw + 4 * n4 + 256 + 2 * n_st));
+  const size_t n_pr = align256((size_t)F * c->N * c->m * 4);
+  HIP_TRY(hipMalloc((void**)&tmp, n_fsw + 4 * n4 + 256 + 2 * n_st + n_pr));
   char* st_in = tmp + n_fsw + 4 * n4 + 256;
   char* st_out = st_in + n_st;
+  float* prior = (float*)(st_out + n_st);
   uint8_t* fsw = (uint8_t*)tmp;
   uint32_t* active = (uint32_t*)(tmp + n_fsw);
   uint32_t* unsat = (uint32_t*)(tmp + n_fsw + n4);
@@ -478,16 +582,17 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   int* nact = (int*)(tmp + n_fsw + 4 * n4);
   const unsigned fb = cdiv(F, 256);
   hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, active, unsat, mism, alist, nact, (int32_t*)nullptr,
-                     (uint32_t*)nullptr);
-  bool ok = dispatch(c->m, c->kmax, [&](auto impl) {
+                     (uint32_t*)nullptr, (int*)nullptr);
+  launch_prior(c, F, llr, prior, s);
+  bool ok = dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
     using I = decltype(impl);
     if (mode == LDPC_FD_MODE_PLAIN) {
       I::var_plain(cd, F, llr, c2v_in, v2c_out, hard, fsw, nullptr, c2v_in ? 0 : 1, s);
       if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
       I::check_plain(cd, F, v2c_out, c2v_out, nullptr, s);
     } else if (prec == LDPC_FD_FP32) {
-      I::template fused<float>(cd, F, llr, c2v_in, c2v_out, hard, fsw, alist, nact, c2v_in ? 0 : 1,
-                               c2v_in ? 1 : 0, 1, s);
+      I::template fused<float>(cd, F, prior, c2v_in, c2v_out, hard, fsw, alist, nact, c2v_in ? 0 : 1,
+                               c2v_in ? 1 : 0, 1, c->blocks, s);
       if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, alist, nact, nullptr, s);
     } else {
       // round the imported state to the storage type, run the pass on it, widen the result
@@ -495,8 +600,8 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
         using S = decltype(tag);
         const unsigned g = (unsigned)std::min<size_t>((n_msg / 4 + 255) / 256, 65536);
         if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, (S*)st_in, n_msg / 4);
-        I::template fused<S>(cd, F, llr, c2v_in ? (const S*)st_in : nullptr, (S*)st_out, hard, fsw, alist, nact,
-                             c2v_in ? 0 : 1, c2v_in ? 1 : 0, 1, s);
+        I::template fused<S>(cd, F, prior, c2v_in ? (const S*)st_in : nullptr, (S*)st_out, hard, fsw, alist, nact,
+                             c2v_in ? 0 : 1, c2v_in ? 1 : 0, 1, c->blocks, s);
         hipLaunchKernelGGL((k_convert<S, float>), dim3(g), dim3(256), 0, s, (const S*)st_out, c2v_out, n_msg / 4);
       };
       if (prec == LDPC_FD_FP16) run(_Float16{}); else run(bf16_t{});
@@ -509,6 +614,47 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   if (e1 != hipSuccess) return fail(LDPC_FD_E_HIP, std::string("round: ") + hipGetErrorString(e1));
   if (e2 != hipSuccess) return fail(LDPC_FD_E_HIP, std::string("hipFree: ") + hipGetErrorString(e2));
   return LDPC_FD_OK;
+}
+
+int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
+  if (!c) return fail(LDPC_FD_E_INVALID, "code is NULL");
+  {
+    std::lock_guard<std::mutex> lock(c->gmu);
+    c->drop_graphs();
+  }
+  switch (key) {
+    case LDPC_FD_TUNE_LANE_ENTRIES:
+      if (value != 4 && value != 8 && value != 16) return fail(LDPC_FD_E_INVALID, "entries per lane: 4, 8 or 16");
+      if (value > c->q || (value == 16 && c->m == 8) || (value > 4 && c->kmax > 8))
+        return fail(LDPC_FD_E_UNSUPPORTED, "no kernel variant with that many entries per lane for this code");
+      c->logr = value == 4 ? 2 : value == 8 ? 3 : 4;
+      return LDPC_FD_OK;
+    case LDPC_FD_TUNE_GRID_BLOCKS:
+      if (value < 8 || value > (1 << 20)) return fail(LDPC_FD_E_INVALID, "grid blocks outside 8..2^20");
+      c->blocks = value;
+      return LDPC_FD_OK;
+    case LDPC_FD_TUNE_CHUNK:
+      if (value < 1 || value > 1000) return fail(LDPC_FD_E_INVALID, "chunk outside 1..1000");
+      c->chunk = value;
+      return LDPC_FD_OK;
+    case LDPC_FD_TUNE_GRAPHS:
+      if (value != 0 && value != 1) return fail(LDPC_FD_E_INVALID, "graphs: 0 or 1");
+      c->graphs = value;
+      return LDPC_FD_OK;
+    default:
+      return fail(LDPC_FD_E_INVALID, "unknown tuning key");
+  }
+}
+
+int32_t ldpc_fd_get_tuning(ldpc_fd_code c, int32_t key, int32_t* value) {
+  if (!c || !value) return fail(LDPC_FD_E_INVALID, "NULL argument");
+  switch (key) {
+    case LDPC_FD_TUNE_LANE_ENTRIES: *value = 1 << c->logr; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_GRID_BLOCKS: *value = c->blocks; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_CHUNK: *value = c->chunk; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_GRAPHS: *value = c->graphs; return LDPC_FD_OK;
+    default: return fail(LDPC_FD_E_INVALID, "unknown tuning key");
+  }
 }
 
 int32_t ldpc_fd_profile_enable(int32_t on) {

@@ -26,7 +26,11 @@ struct Geo {
   static constexpr int LOGL = LOGQ - LOGR;
   static constexpr int L = 1 << LOGL;
   static constexpr int T = 64 / L;
-  static constexpr int QP = Q + 4;  // LDS row pitch in floats (16-byte aligned rows)
+  // LDS: one row of Q floats per frame (pitch Q, a power of two); entry z of
+  // frame fl lives at z ^ swz(fl), which spreads the frames of a wave over the
+  // banks and keeps runs of 4 consecutive z contiguous (swz is a multiple of 4).
+  static constexpr int QP = Q;
+  static __device__ __forceinline__ int swz(int fl) { return (fl << 2) & (Q - 4); }
   static_assert(LOGR >= 2 && LOGL >= 0 && LOGL <= 6, "bad geometry");
   static __host__ __device__ constexpr bool lane_bit(int b) { return b >= 2 && b < 2 + LOGL; }
   static __host__ __device__ constexpr int lane_shift(int b) { return b - 2; }
@@ -59,6 +63,45 @@ __device__ __forceinline__ float lane_xor(float v, int mask) {
     default:
       return __int_as_float(__builtin_amdgcn_ds_bpermute((lane_id() ^ 32) << 2, iv));
   }
+}
+
+// v[r] += c * v[r] of lane (this lane xor MASK), for all r: one
+// v_fmac_f32_dpp per register for quad-local masks (1, 2).  A single s_nop 1
+// ahead of the block covers the DPP read of a VGPR written by the preceding
+// VALU instruction; inside the block every instruction reads a register not
+// written earlier in the block.
+#define LFD_DPP1 "quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n"
+#define LFD_DPP2 "quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n"
+#define LFD_F(i, c, D) "v_fmac_f32_dpp %" #i ", %" #i ", %" #c " " D
+#define LFD_BLK4(c, D) LFD_F(0, c, D) LFD_F(1, c, D) LFD_F(2, c, D) LFD_F(3, c, D)
+#define LFD_BLK8(c, D) LFD_BLK4(c, D) LFD_F(4, c, D) LFD_F(5, c, D) LFD_F(6, c, D) LFD_F(7, c, D)
+#define LFD_BLK16(c, D)                                                                    \
+  LFD_BLK8(c, D) LFD_F(8, c, D) LFD_F(9, c, D) LFD_F(10, c, D) LFD_F(11, c, D) LFD_F(12, c, D) \
+  LFD_F(13, c, D) LFD_F(14, c, D) LFD_F(15, c, D)
+#define LFD_V4(v) "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3])
+#define LFD_V8(v) LFD_V4(v), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7])
+#define LFD_V16(v) LFD_V8(v), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), \
+                   "+v"(v[13]), "+v"(v[14]), "+v"(v[15])
+
+template <int R>
+__device__ __forceinline__ void lane_fmac(float (&v)[R], float c, int mask) {
+  if (mask == 1 || mask == 2) {
+    if constexpr (R == 4) {
+      if (mask == 1) asm volatile("s_nop 1\n" LFD_BLK4(4, LFD_DPP1) : LFD_V4(v) : "v"(c));
+      else asm volatile("s_nop 1\n" LFD_BLK4(4, LFD_DPP2) : LFD_V4(v) : "v"(c));
+      return;
+    } else if constexpr (R == 8) {
+      if (mask == 1) asm volatile("s_nop 1\n" LFD_BLK8(8, LFD_DPP1) : LFD_V8(v) : "v"(c));
+      else asm volatile("s_nop 1\n" LFD_BLK8(8, LFD_DPP2) : LFD_V8(v) : "v"(c));
+      return;
+    } else if constexpr (R == 16) {
+      if (mask == 1) asm volatile("s_nop 1\n" LFD_BLK16(16, LFD_DPP1) : LFD_V16(v) : "v"(c));
+      else asm volatile("s_nop 1\n" LFD_BLK16(16, LFD_DPP2) : LFD_V16(v) : "v"(c));
+      return;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = __builtin_fmaf(c, lane_xor(v[r], mask), v[r]);
 }
 
 // Broadcast the value of the frame's first lane (zl = 0) to its L lanes.
@@ -98,9 +141,7 @@ __device__ __forceinline__ void conv_prior(float (&v)[G::R], const float (&t)[G:
   for (int b = 0; b < G::LOGQ; ++b) {
     const float tb = t[b];
     if (G::lane_bit(b)) {
-      const int mask = 1 << G::lane_shift(b);
-#pragma unroll
-      for (int r = 0; r < G::R; ++r) v[r] = __builtin_fmaf(tb, lane_xor(v[r], mask), v[r]);
+      lane_fmac<G::R>(v, tb, 1 << G::lane_shift(b));
     } else {
       const int rb = 1 << G::reg_bit(b);
 #pragma unroll
@@ -115,16 +156,19 @@ __device__ __forceinline__ void conv_prior(float (&v)[G::R], const float (&t)[G:
   }
 }
 
-// ---- unnormalised Walsh-Hadamard transform: V(z) = sum_x v(x) (-1)^(z.x) ------
+// ---- unnormalised Walsh-Hadamard transform, up to a lane sign ----------------
+// Returns s(z) V(z) with V(z) = sum_x v(x) (-1)^(z.x) and s(z) = (-1)^popcount(zl)
+// (zl = the lane bits of z): along a lane bit each lane forms own +/- partner,
+// which is the butterfly output negated on the lanes whose bit is set; the
+// flips of later stages factor out because both members of every later pair
+// share the bit.  Products of two such transforms carry s(z)^2 = 1.
 template <class G>
-__device__ __forceinline__ void wht(float (&v)[G::R], int zl) {
+__device__ __forceinline__ void wht_s(float (&v)[G::R], int zl) {
 #pragma unroll
   for (int b = 0; b < G::LOGQ; ++b) {
     if (G::lane_bit(b)) {
       const int sh = G::lane_shift(b);
-      const float s = ((zl >> sh) & 1) ? -1.0f : 1.0f;
-#pragma unroll
-      for (int r = 0; r < G::R; ++r) v[r] = __builtin_fmaf(s, v[r], lane_xor(v[r], 1 << sh));
+      lane_fmac<G::R>(v, ((zl >> sh) & 1) ? -1.0f : 1.0f, 1 << sh);
     } else {
       const int rb = 1 << G::reg_bit(b);
 #pragma unroll
@@ -141,27 +185,51 @@ __device__ __forceinline__ void wht(float (&v)[G::R], int zl) {
 
 // ---- label permutation through LDS -------------------------------------------
 // out(z) = in(A z) for a GF(2)-linear map A given by its columns col[b] = A e_b
-// (a wave-uniform 8-byte word, byte b).  `row` is this lane's frame row in LDS.
-// Lanes of one frame exchange entries through the frame's LDS row; LDS
-// operations of a wave execute in order, and wave barriers keep the compiler
-// from moving a lane's accesses across the exchange.
+// (a wave-uniform 8-byte word, byte b).  `rb` is the element index of this
+// lane's frame row, `cf` the frame's swizzle.  A z = A z_reg ^ A z_lane, so a
+// read index is (rb | (A z_lane ^ cf)) ^ A z_reg: one XOR per element with a
+// wave-uniform A z_reg.  Lanes of one frame exchange entries through the row;
+// LDS operations of a wave execute in order, and wave barriers keep the
+// compiler from moving a lane's accesses across the exchange.
+typedef __attribute__((address_space(3))) const float lds_float;
+
+// LDS (address-space 3) byte address of a pointer into shared memory.
+__device__ __forceinline__ uint32_t lds_addr(const float* p) {
+  return (uint32_t)(size_t)((__attribute__((address_space(3))) const float*)p);
+}
+
 template <class G>
-__device__ __forceinline__ void permute(float (&v)[G::R], float* row, int zl, uint64_t cols) {
-  __builtin_amdgcn_wave_barrier();
+__device__ __forceinline__ void lds_put(float* lds, int rb, int cf, int zl, const float (&v)[G::R]) {
 #pragma unroll
-  for (int r = 0; r < G::R; ++r) row[G::z_of(zl, r)] = v[r];
+  for (int h = 0; h < G::R / 4; ++h) {
+    const int z0 = (zl << 2) | (h << (2 + G::LOGL));
+    *reinterpret_cast<float4*>(lds + (rb | (z0 ^ cf))) = make_float4(v[4 * h], v[4 * h + 1], v[4 * h + 2], v[4 * h + 3]);
+  }
+}
+
+template <class G>
+__device__ __forceinline__ void permute(float (&v)[G::R], float* lds, int rb, int cf, int zl, uint64_t cols) {
+  __builtin_amdgcn_wave_barrier();
+  lds_put<G>(lds, rb, cf, zl, v);
   __builtin_amdgcn_wave_barrier();
   int pl = 0;
 #pragma unroll
   for (int lb = 0; lb < G::LOGL; ++lb)
     if ((zl >> lb) & 1) pl ^= (int)((cols >> (8 * (2 + lb))) & 0xFF);
+  // LDS byte address of the row entry, so each gathered element costs one XOR.
+  // Rows start at multiples of 4Q bytes from the array base, which is itself
+  // 4Q-aligned (the array is the kernel's only LDS), so XOR-ing an offset
+  // below 4Q stays inside the row.  The empty asm keeps the compiler from
+  // re-factoring the shift out of the XOR.
+  uint32_t lbase4 = lds_addr(lds) + ((uint32_t)(rb | (pl ^ cf)) << 2);
+  asm volatile("" : "+v"(lbase4));
 #pragma unroll
   for (int r = 0; r < G::R; ++r) {
-    int pr = 0;
+    uint32_t pr = 0;
 #pragma unroll
-    for (int rb = 0; rb < G::LOGR; ++rb)
-      if ((r >> rb) & 1) pr ^= (int)((cols >> (8 * G::zbit_of_regbit(rb))) & 0xFF);
-    v[r] = row[pr ^ pl];
+    for (int rbit = 0; rbit < G::LOGR; ++rbit)
+      if ((r >> rbit) & 1) pr ^= (uint32_t)((cols >> (8 * G::zbit_of_regbit(rbit))) & 0xFF);
+    v[r] = *reinterpret_cast<const lds_float*>((size_t)(lbase4 ^ (pr << 2)));
   }
   __builtin_amdgcn_wave_barrier();
 }

@@ -24,6 +24,7 @@ struct DevCode {
   const uint8_t* ginv;     // [256]
   const uint8_t* gexp;     // [512]
   const uint16_t* glog;    // [256]
+  const uint32_t* e_pack;  // [E] variable | label << 24
 };
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -48,28 +49,34 @@ __device__ __forceinline__ void prior_coeffs(const float* llr_fv, float (&t)[G::
 
 // Tentative decision from Y = P0 (*) X_c'v and Xo = X_cv (both variable
 // coordinates, positive scale irrelevant): Q = WHT(WHT(Y) . WHT(Xo)) is the
-// Fourier image of the posterior up to a positive factor.
+// Fourier image of the posterior up to a positive factor.  The lane signs of
+// the first two transforms cancel in the product; the third is undone with
+// s(z) before the values are written to the frame's LDS row, from which the
+// 3m points are read.
 template <class G>
-__device__ __forceinline__ void decide(const float (&Y)[G::R], float (&Xo)[G::R], float* row, int zl,
-                                       uint64_t cols_a, uint64_t cols_b, int& hard, int& fa, int& fb) {
+__device__ __forceinline__ void decide(const float (&Y)[G::R], float (&Xo)[G::R], float* lds, int rb, int cf,
+                                       int zl, uint64_t cols_a, uint64_t cols_b, int& hard, int& fa, int& fb) {
   float A[G::R];
 #pragma unroll
   for (int r = 0; r < G::R; ++r) A[r] = Y[r];
-  wht<G>(A, zl);
-  wht<G>(Xo, zl);
+  wht_s<G>(A, zl);
+  wht_s<G>(Xo, zl);
 #pragma unroll
   for (int r = 0; r < G::R; ++r) A[r] *= Xo[r];
-  wht<G>(A, zl);
-  __builtin_amdgcn_wave_barrier();
+  wht_s<G>(A, zl);
+  const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
 #pragma unroll
-  for (int r = 0; r < G::R; ++r) row[G::z_of(zl, r)] = A[r];
+  for (int r = 0; r < G::R; ++r) A[r] *= sz;
+  __builtin_amdgcn_wave_barrier();
+  lds_put<G>(lds, rb, cf, zl, A);
   __builtin_amdgcn_wave_barrier();
   hard = 0; fa = 0; fb = 0;
+  const int rcf = rb | cf;
 #pragma unroll
   for (int i = 0; i < G::LOGQ; ++i) {
-    hard |= (row[1 << i] < 0.0f) << i;
-    fa |= (row[(cols_a >> (8 * i)) & 0xFF] < 0.0f) << i;
-    fb |= (row[(cols_b >> (8 * i)) & 0xFF] < 0.0f) << i;
+    hard |= (lds[rcf ^ (1 << i)] < 0.0f) << i;
+    fa |= (lds[rcf ^ (int)((cols_a >> (8 * i)) & 0xFF)] < 0.0f) << i;
+    fb |= (lds[rcf ^ (int)((cols_b >> (8 * i)) & 0xFF)] < 0.0f) << i;
   }
   __builtin_amdgcn_wave_barrier();
 }
@@ -104,7 +111,7 @@ __global__ __launch_bounds__(256) void k_var_plain(DevCode cd, int F, const floa
   const bool valid = f < F && (active == nullptr || active[f] != 0u);
   if (__builtin_amdgcn_ballot_w64(valid) == 0) return;
   if (f >= F) f = F - 1;
-  float* row = lds + (wave * G::T + fl) * G::QP;
+  const int rb = (wave * G::T + fl) * G::QP, cf = G::swz(fl);
   const int e1 = uni(cd.v_edges[2 * v]), e2 = uni(cd.v_edges[2 * v + 1]);
   float t[G::LOGQ];
   prior_coeffs<G>(llr + ((size_t)f * cd.N + v) * G::LOGQ, t);
@@ -135,7 +142,7 @@ __global__ __launch_bounds__(256) void k_var_plain(DevCode cd, int F, const floa
   conv_prior<G>(Y2, t);  // to check c2: prior (*) message from c1
   int hd, fa, fb2;
   const int h1 = uni(cd.e_label[e1]), h2 = uni(cd.e_label[e2]);
-  decide<G>(Y1, X1, row, zl, uni64(cd.colsT[h1]), uni64(cd.colsT[h2]), hd, fa, fb2);
+  decide<G>(Y1, X1, lds, rb, cf, zl, uni64(cd.colsT[h1]), uni64(cd.colsT[h2]), hd, fa, fb2);
   normalise_gamma<G>(Y1);
   normalise_gamma<G>(Y2);
   if (valid) {
@@ -168,7 +175,7 @@ __global__ __launch_bounds__(256) void k_check_plain(DevCode cd, int F, const fl
   const bool valid = f < F && (active == nullptr || active[f] != 0u);
   if (__builtin_amdgcn_ballot_w64(valid) == 0) return;
   if (f >= F) f = F - 1;
-  float* row = lds + (wave * G::T + fl) * G::QP;
+  const int rb = (wave * G::T + fl) * G::QP, cf = G::swz(fl);
   const int e0 = uni(cd.row_ptr[c]), deg = uni(cd.row_ptr[c + 1]) - e0;
   const size_t fb = (size_t)f * cd.E * G::Q;
   float st[KMAX][G::R];
@@ -182,7 +189,7 @@ __global__ __launch_bounds__(256) void k_check_plain(DevCode cd, int F, const fl
       const int e = e0 + j;
       const int h = uni(cd.e_label[e]);
       load_msg<G, float>(v2c + fb + (size_t)e * G::Q, zl, st[j]);
-      permute<G>(st[j], row, zl, uni64(cd.colsT[h]));
+      permute<G>(st[j], lds, rb, cf, zl, uni64(cd.colsT[h]));
 #pragma unroll
       for (int r = 0; r < G::R; ++r) {
         smag[r] += __builtin_fabsf(st[j][r]);
@@ -201,7 +208,7 @@ __global__ __launch_bounds__(256) void k_check_plain(DevCode cd, int F, const fl
         const float mag = __builtin_amdgcn_fmed3f(smag[r] - __builtin_fabsf(st[j][r]), 0.0f, kLmax);
         o[r] = __uint_as_float(((ssgn[r] ^ __float_as_uint(st[j][r])) & 0x80000000u) | __float_as_uint(mag));
       }
-      permute<G>(o, row, zl, uni64(cd.colsT[hinv]));
+      permute<G>(o, lds, rb, cf, zl, uni64(cd.colsT[hinv]));
       if (valid) store_msg<G, float>(c2v + fb + (size_t)e * G::Q, zl, o);
     }
   }
@@ -216,45 +223,66 @@ __global__ __launch_bounds__(256) void k_check_plain(DevCode cd, int F, const fl
 //   first:   round 0 -> 1 (Lambda_vc = Lambda^(0), no decision).
 //   decide:  form the decision of round l.
 //   write:   store round l+1 (off in the last pass).
+// Loads of one edge: the other edge's message, the own message (owner visits
+// of a deciding pass) and the LLRs of the variable.
+template <class G, typename S>
+struct EdgeLoads {
+  float x[G::R];
+  float o[G::R];
+  float l[G::LOGQ];   // prior factors t_i = tanh(L_i / 2) of the variable
+};
+
+template <class G, typename S>
+__device__ __forceinline__ void issue_edge(const DevCode& cd, const float* __restrict__ tp, const S* __restrict__ cin,
+                                           size_t fb, int f, int e, int first, int decide_flag, int zl,
+                                           EdgeLoads<G, S>& L) {
+  const int v = uni(cd.e_var[e]);
+  const int eo = uni(cd.e_other[e]);
+  const float* lp = tp + ((size_t)f * cd.N + v) * G::LOGQ;
+#pragma unroll
+  for (int i = 0; i < G::LOGQ; ++i) L.l[i] = lp[i];
+  if (!first) load_msg<G, S>(cin + fb + (size_t)eo * G::Q, zl, L.x);
+  if (decide_flag && e < eo) load_msg<G, S>(cin + fb + (size_t)e * G::Q, zl, L.o);
+}
+
 template <class G, int KMAX, typename S>
-__device__ __forceinline__ void fused_item(const DevCode& cd, const float* __restrict__ llr,
+__device__ __forceinline__ void fused_item(const DevCode& cd, const float* __restrict__ tp,
                                            const S* __restrict__ cin, S* __restrict__ cout,
                                            uint8_t* __restrict__ hard, uint8_t* __restrict__ fsw, int f,
-                                           bool valid, int c, float* row, int zl, int first, int decide_flag,
-                                           int write) {
+                                           bool valid, int c, float* lds, int rb, int cf, int zl, int first,
+                                           int decide_flag, int write) {
   const int e0 = uni(cd.row_ptr[c]), deg = uni(cd.row_ptr[c + 1]) - e0;
   const size_t fb = (size_t)f * cd.E * G::Q;
-  float st[KMAX][G::R];
+  float st[KMAX][G::R];   // Lambda~_vc of each edge (check coordinates)
   float smag[G::R];
-  uint32_t ssgn[G::R];
 #pragma unroll
-  for (int r = 0; r < G::R; ++r) { smag[r] = 0.0f; ssgn[r] = 0u; }
+  for (int r = 0; r < G::R; ++r) smag[r] = 0.0f;
+  // edge j+1's loads are in flight while edge j is computed
+  EdgeLoads<G, S> nxt;
+  issue_edge<G, S>(cd, tp, cin, fb, f, e0, first, decide_flag, zl, nxt);
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j < deg) {
       const int e = e0 + j;
+      const EdgeLoads<G, S> cur = nxt;
+      if (j + 1 < deg) issue_edge<G, S>(cd, tp, cin, fb, f, e + 1, first, decide_flag, zl, nxt);
       const int v = uni(cd.e_var[e]);
       const int eo = uni(cd.e_other[e]);
       const int h = uni(cd.e_label[e]);
       float t[G::LOGQ];
-      prior_coeffs<G>(llr + ((size_t)f * cd.N + v) * G::LOGQ, t);
-      if (first) {
 #pragma unroll
-        for (int r = 0; r < G::R; ++r) st[j][r] = (r == 0 && zl == 0) ? 1.0f : 0.0f;
-      } else {
-        load_msg<G, S>(cin + fb + (size_t)eo * G::Q, zl, st[j]);
+      for (int i = 0; i < G::LOGQ; ++i) t[i] = cur.l[i];   // prior factors tanh(L_i / 2)
 #pragma unroll
-        for (int r = 0; r < G::R; ++r) st[j][r] = gamma_inv(st[j][r]);
-      }
+      for (int r = 0; r < G::R; ++r)
+        st[j][r] = first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
       conv_prior<G>(st[j], t);
       if (decide_flag && e < eo) {
-        float Xo[G::R];
-        load_msg<G, S>(cin + fb + (size_t)e * G::Q, zl, Xo);
+        float xo[G::R];
 #pragma unroll
-        for (int r = 0; r < G::R; ++r) Xo[r] = gamma_inv(Xo[r]);
+        for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
         int hd, fa, fo;
         const int ho = uni(cd.e_label[eo]);
-        decide<G>(st[j], Xo, row, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
+        decide<G>(st[j], xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
         if (valid && zl == 0) {
           hard[(size_t)f * cd.N + v] = (uint8_t)hd;
           fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
@@ -262,15 +290,22 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
         }
       }
       normalise_gamma<G>(st[j]);
-      permute<G>(st[j], row, zl, uni64(cd.colsT[h]));
+      permute<G>(st[j], lds, rb, cf, zl, uni64(cd.colsT[h]));
 #pragma unroll
-      for (int r = 0; r < G::R; ++r) {
-        smag[r] += __builtin_fabsf(st[j][r]);
-        ssgn[r] ^= __float_as_uint(st[j][r]);
-      }
+      for (int r = 0; r < G::R; ++r) smag[r] += __builtin_fabsf(st[j][r]);
     }
   }
   if (!write) return;
+  // GF(2) sign of the full sum (XOR over the check's edges)
+  uint32_t ssgn[G::R];
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) ssgn[r] = 0u;
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    if (j < deg) {
+#pragma unroll
+      for (int r = 0; r < G::R; ++r) ssgn[r] ^= __float_as_uint(st[j][r]);
+    }
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j < deg) {
@@ -282,7 +317,7 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
         const float mag = __builtin_amdgcn_fmed3f(smag[r] - __builtin_fabsf(st[j][r]), 0.0f, kLmax);
         o[r] = __uint_as_float(((ssgn[r] ^ __float_as_uint(st[j][r])) & 0x80000000u) | __float_as_uint(mag));
       }
-      permute<G>(o, row, zl, uni64(cd.colsT[hinv]));
+      permute<G>(o, lds, rb, cf, zl, uni64(cd.colsT[hinv]));
       if (valid) store_msg<G, S>(cout + fb + (size_t)e * G::Q, zl, o);
     }
   }
@@ -296,12 +331,15 @@ constexpr int kXcds = 8;
 // other edge of its variable, and by its own check at the owner visit) come
 // from the same XCD's L2.  gridDim.x must be a multiple of 8.
 template <class G, int KMAX, typename S>
-__global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restrict__ llr,
+__global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restrict__ tp,
                                                const S* __restrict__ cin, S* __restrict__ cout,
                                                uint8_t* __restrict__ hard, uint8_t* __restrict__ fsw,
                                                const int* __restrict__ alist, const int* __restrict__ nact_p,
-                                               int first, int decide_flag, int write) {
+                                               int first, int decide_flag, int write, const int* __restrict__ ell_p,
+                                               int max_iter) {
   extern __shared__ float lds[];
+  // write < 0: store round l+1 unless the device round counter l has reached max_iter
+  if (write < 0) write = *ell_p < max_iter;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int waves = blockDim.x >> 6;
   const int nact = *nact_p;
@@ -311,23 +349,65 @@ __global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restri
   const long groups_x = (groups - xcd + kXcds - 1) / kXcds;
   const long items = groups_x * cd.M;
   const int fl = lane / G::L, zl = lane % G::L;
-  float* row = lds + (wave * G::T + fl) * G::QP;
+  const int rb = (wave * G::T + fl) * G::QP, cf = G::swz(fl);
   for (long it = (long)(blockIdx.x / kXcds) * waves + wave; it < items; it += stride) {
     const int g = xcd + kXcds * (int)(it / cd.M);
     const int c = (int)(it % cd.M);
     const int slot = g * G::T + fl;
     const bool valid = slot < nact;
     const int f = alist[valid ? slot : nact - 1];
-    fused_item<G, KMAX, S>(cd, llr, cin, cout, hard, fsw, f, valid, c, row, zl, first, decide_flag, write);
+    fused_item<G, KMAX, S>(cd, tp, cin, cout, hard, fsw, f, valid, c, lds, rb, cf, zl, first, decide_flag, write);
+  }
+}
+
+// Syndromes of the tentative decision, for codes whose rows do not fit in LDS
+// (one thread per (active frame, check)): direct s_c = sum_{v in V_c} h_cv x^_v
+// and Fourier word = XOR of per-edge sign words.  Flags the frame when either
+// is nonzero or they differ (unsat / mism must be zero on entry).
+__global__ void k_syndrome(DevCode cd, const uint8_t* __restrict__ hard, const uint8_t* __restrict__ fsw,
+                           uint8_t* __restrict__ synd, uint8_t* __restrict__ fsynd,
+                           uint32_t* __restrict__ unsat, uint32_t* __restrict__ mism,
+                           const int* __restrict__ alist, const int* __restrict__ nact_p, int F_all,
+                           const uint32_t* __restrict__ active) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nact = nact_p ? *nact_p : F_all;
+  if (i >= (long)nact * cd.M) return;
+  const int slot = (int)(i / cd.M), c = (int)(i % cd.M);
+  const int f = alist ? alist[slot] : slot;
+  if (active && !active[f]) return;
+  const int e0 = cd.row_ptr[c], e1 = cd.row_ptr[c + 1];
+  int s = 0, sf = 0;
+  for (int e = e0; e < e1; ++e) {
+    const int x = hard[(size_t)f * cd.N + cd.e_var[e]];
+    if (x) s ^= cd.gexp[cd.glog[cd.e_label[e]] + cd.glog[x]];
+    sf ^= fsw[(size_t)f * cd.E + e];
+  }
+  synd[(size_t)f * cd.M + c] = (uint8_t)s;
+  if (fsynd) fsynd[(size_t)f * cd.M + c] = (uint8_t)sf;
+  if (s | sf) atomicOr(&unsat[f], 1u);
+  if (s != sf) atomicOr(&mism[f], 1u);
+}
+
+// INITIALIZATION (Sec. 3.2): the initial message Lambda_v^(0) is Gamma of the
+// Fourier transform of the channel pmf, which for BPSK factors over the bits:
+// P_v^(0)(z) = prod_{i in z} tanh(L_{v,i}/2).  The passes keep only these m
+// factors per symbol (the same 4 N m bytes as the LLRs) and apply them as the
+// prior convolution; this kernel forms them once per decode.
+__global__ void k_prior_factors(const float* __restrict__ llr, float* __restrict__ t, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float x = llr[i];
+    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * __builtin_fabsf(x));  // e^-|L|
+    t[i] = __builtin_copysignf((1.0f - e) / (1.0f + e), x);
   }
 }
 
 // Syndromes of the tentative decision, one workgroup per active frame: the
 // frame's hard decisions and per-edge Fourier sign words are staged in LDS
-// (coalesced), then each thread forms checks c = tid, tid + 256, ...:
-// direct s_c = sum_{v in V_c} h_cv x^_v and the Fourier word = XOR of the
-// check's edge words (edges of a check are contiguous).  unsat[f] / mism[f]
-// are set to whether any check is nonzero / any pair differs.
+// (word loads when the rows are word aligned), the field tables once per
+// workgroup; each thread then forms checks c = tid, tid + 256, ...: direct
+// s_c = sum_{v in V_c} h_cv x^_v and the Fourier word = XOR of the check's
+// edge words (edges of a check are contiguous).  unsat[f] / mism[f] are set to
+// whether any check is nonzero / any pair differs.
 __global__ __launch_bounds__(256) void k_syndrome_frames(DevCode cd, const uint8_t* __restrict__ hard,
                                                          const uint8_t* __restrict__ fsw,
                                                          uint8_t* __restrict__ synd, uint8_t* __restrict__ fsynd,
@@ -335,23 +415,40 @@ __global__ __launch_bounds__(256) void k_syndrome_frames(DevCode cd, const uint8
                                                          const int* __restrict__ alist,
                                                          const int* __restrict__ nact_p, int F_all,
                                                          const uint32_t* __restrict__ active) {
-  extern __shared__ uint8_t sm[];
-  uint8_t* sh = sm;            // [N]
-  uint8_t* sw = sm + cd.N;     // [E]
+  extern __shared__ uint32_t smw[];
+  uint8_t* sh = reinterpret_cast<uint8_t*>(smw);   // [N] (rounded up to words)
+  const int nw = (cd.N + 3) >> 2, ew = (cd.E + 3) >> 2;
+  uint8_t* sw = reinterpret_cast<uint8_t*>(smw + nw);  // [E]
+  __shared__ uint8_t s_exp[512];
+  __shared__ uint16_t s_log[256];
+  for (int i = threadIdx.x; i < 512; i += blockDim.x) s_exp[i] = cd.gexp[i];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) s_log[i] = cd.glog[i];
   const int nact = nact_p ? *nact_p : F_all;
+  const bool wN = (cd.N & 3) == 0, wE = (cd.E & 3) == 0;
   for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
     const int f = alist ? alist[slot] : slot;
     if (active && !active[f]) continue;  // uniform over the block
-    for (int i = threadIdx.x; i < cd.N; i += blockDim.x) sh[i] = hard[(size_t)f * cd.N + i];
-    for (int i = threadIdx.x; i < cd.E; i += blockDim.x) sw[i] = fsw[(size_t)f * cd.E + i];
+    if (wN) {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(hard + (size_t)f * cd.N);
+      for (int i = threadIdx.x; i < nw; i += blockDim.x) smw[i] = src[i];
+    } else {
+      for (int i = threadIdx.x; i < cd.N; i += blockDim.x) sh[i] = hard[(size_t)f * cd.N + i];
+    }
+    if (wE) {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(fsw + (size_t)f * cd.E);
+      for (int i = threadIdx.x; i < ew; i += blockDim.x) smw[nw + i] = src[i];
+    } else {
+      for (int i = threadIdx.x; i < cd.E; i += blockDim.x) sw[i] = fsw[(size_t)f * cd.E + i];
+    }
     __syncthreads();
     int bad = 0, mm = 0;
     for (int c = threadIdx.x; c < cd.M; c += blockDim.x) {
       const int e0 = cd.row_ptr[c], e1 = cd.row_ptr[c + 1];
       int s = 0, sf = 0;
       for (int e = e0; e < e1; ++e) {
-        const int x = sh[cd.e_var[e]];
-        if (x) s ^= cd.gexp[cd.glog[cd.e_label[e]] + cd.glog[x]];
+        const uint32_t pk = cd.e_pack[e];
+        const int x = sh[pk & 0xFFFFFFu];
+        if (x) s ^= s_exp[s_log[pk >> 24] + s_log[x]];
         sf ^= sw[e];
       }
       synd[(size_t)f * cd.M + c] = (uint8_t)s;
@@ -368,36 +465,6 @@ __global__ __launch_bounds__(256) void k_syndrome_frames(DevCode cd, const uint8
   }
 }
 
-// ---------------------------------------------------------------------------
-// Syndromes of the tentative decision (one thread per (active frame, check)):
-// direct s_c = sum_{v in V_c} h_cv x^_v and Fourier word = XOR of per-edge
-// sign words.  Flags the frame when either is nonzero or they differ.
-__global__ void k_syndrome(DevCode cd, const uint8_t* __restrict__ hard, const uint8_t* __restrict__ fsw,
-                           uint8_t* __restrict__ synd, uint8_t* __restrict__ fsynd,
-                           uint32_t* __restrict__ unsat, uint32_t* __restrict__ mism,
-                           const int* __restrict__ alist, const int* __restrict__ nact_p, int F_all,
-                           const uint32_t* __restrict__ active) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int nact = nact_p ? *nact_p : F_all;
-  if (i >= (long)nact * cd.M) return;
-  const int slot = (int)(i / cd.M), c = (int)(i % cd.M);
-  const int f = alist ? alist[slot] : slot;
-  if (active && !active[f]) return;
-  const int e0 = cd.row_ptr[c], e1 = cd.row_ptr[c + 1];
-  int s = 0, sf = 0;
-  const int qm1 = (1 << cd.m) - 1;
-  for (int e = e0; e < e1; ++e) {
-    const int x = hard[(size_t)f * cd.N + cd.e_var[e]];
-    const int h = cd.e_label[e];
-    if (x) s ^= cd.gexp[(cd.glog[h] + cd.glog[x]) % qm1];
-    sf ^= fsw[(size_t)f * cd.E + e];
-  }
-  synd[(size_t)f * cd.M + c] = (uint8_t)s;
-  if (fsynd) fsynd[(size_t)f * cd.M + c] = (uint8_t)sf;
-  if (s | sf) atomicOr(&unsat[f], 1u);
-  if (s != sf) atomicOr(&mism[f], 1u);
-}
-
 // Elementwise conversion between message storage types (n4 groups of 4).
 template <typename Sin, typename Sout>
 __global__ void k_convert(const Sin* __restrict__ in, Sout* __restrict__ out, size_t n4) {
@@ -409,9 +476,10 @@ __global__ void k_convert(const Sin* __restrict__ in, Sout* __restrict__ out, si
 }
 
 __global__ void k_init_frames(int F, uint32_t* active, uint32_t* unsat, uint32_t* mism, int* alist,
-                              int* nact, int32_t* iters, uint32_t* status) {
+                              int* nact, int32_t* iters, uint32_t* status, int* ell) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f == 0 && nact) *nact = F;
+  if (f == 0 && ell) *ell = 1;
   if (f >= F) return;
   if (active) active[f] = 1u;
   unsat[f] = 0u;
@@ -443,11 +511,14 @@ __global__ void k_retire_plain(int F, int ell, int max_iter, uint32_t* active, u
 
 // FUSED decoder: stopping rule for round ell and stable compaction of the
 // active list (single workgroup of 1024 threads).
+// With ell_p set, the round number is read from (and then advanced in) device
+// memory, so that a captured chunk of rounds replays unchanged.
 __global__ __launch_bounds__(1024) void k_retire_compact(int ell, int max_iter, int* alist, int* tmp,
                                                          int* nact_p, uint32_t* unsat, uint32_t* mism,
-                                                         int32_t* iters, uint32_t* status) {
+                                                         int32_t* iters, uint32_t* status, int* ell_p) {
   __shared__ int wsum[16];
   __shared__ int base_s;
+  if (ell_p) ell = *ell_p;
   const int nact = *nact_p;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid == 0) base_s = 0;
@@ -483,7 +554,10 @@ __global__ __launch_bounds__(1024) void k_retire_compact(int ell, int max_iter, 
   const int total = base_s;
   for (int i = tid; i < total; i += 1024) alist[i] = tmp[i];
   __syncthreads();
-  if (tid == 0) *nact_p = total;
+  if (tid == 0) {
+    *nact_p = total;
+    if (ell_p) *ell_p = ell + 1;
+  }
 }
 
 }  // namespace ldpcfd

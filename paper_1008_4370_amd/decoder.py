@@ -21,6 +21,7 @@ PREC = {"fp32": 0, "fp16": 1, "bf16": 2}
 MODE = {"plain": 0, "fused": 1}
 STATUS_CONVERGED, STATUS_MISMATCH = 1, 2
 K_FUSED, K_CHECK, K_VAR = 0, 1, 2
+TUNE = {"lane_entries": 0, "grid_blocks": 1, "chunk": 2, "graphs": 3}
 
 _lib = None
 _c_void_p, _i32, _i64, _u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
@@ -34,6 +35,8 @@ _SIGS = {
                               _c_void_p, _c_void_p, _i64, _c_void_p]),
     "ldpc_fd_round": (_i32, [_c_void_p, _i32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
                              _c_void_p, _i32, _i32, _c_void_p]),
+    "ldpc_fd_set_tuning": (_i32, [_c_void_p, _i32, _i32]),
+    "ldpc_fd_get_tuning": (_i32, [_c_void_p, _i32, ctypes.POINTER(_i32)]),
     "ldpc_fd_profile_enable": (_i32, [_i32]),
     "ldpc_fd_profile_read": (_i32, [_i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
     "ldpc_fd_last_error": (ctypes.c_char_p, []),
@@ -99,6 +102,18 @@ class Code:
         _check(lib().ldpc_fd_code_info(self.handle, *[ctypes.byref(v) for v in vals]))
         self.E, self.kmax = vals[3].value, vals[4].value
         self.q = 1 << self.m
+
+    def set_tuning(self, **kw):
+        for k, v in kw.items():
+            _check(lib().ldpc_fd_set_tuning(self.handle, TUNE[k], int(v)))
+
+    def get_tuning(self) -> dict:
+        out = {}
+        for k, key in TUNE.items():
+            v = _i32()
+            _check(lib().ldpc_fd_get_tuning(self.handle, key, ctypes.byref(v)))
+            out[k] = v.value
+        return out
 
     @classmethod
     def from_synth(cls, code):

@@ -239,3 +239,24 @@ def test_edge_cases():
                                 D._ptr(dec.iters), D._ptr(dec.status), D._ptr(dec.workspace), dec.ws_bytes, None)
     assert rc == D.E_INVALID
     gcode.close()
+
+
+def test_graph_replay_matches_eager_launches():
+    """Captured round chunks replayed several times, with eager decodes and
+    synchronisations in between, give exactly the eager results every time."""
+    b = synth.make_batch("gf64_n1000", point=1, frames=300)
+    gcode = D.Code.from_synth(b.code)
+    L = _dev(b.llr)
+    gcode.set_tuning(graphs=0)
+    ref = {k: v.cpu().numpy() for k, v in D.decode(gcode, L, 40, prec="fp32").items()}
+    gcode.set_tuning(graphs=1)
+    dec = D.Decoder(gcode, 300, "fp32", "fused")
+    for rep in range(4):
+        out = {k: v.cpu().numpy() for k, v in dec(L, 40).items()}
+        for k in ref:
+            assert np.array_equal(out[k], ref[k]), (rep, k)
+        gcode.set_tuning(graphs=0)
+        eager = {k: v.cpu().numpy() for k, v in D.decode(gcode, L, 40, prec="fp32").items()}
+        assert all(np.array_equal(eager[k], ref[k]) for k in ref)
+        gcode.set_tuning(graphs=1)
+    gcode.close()
