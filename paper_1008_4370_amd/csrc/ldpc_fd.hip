@@ -119,12 +119,12 @@ struct Impl {
     return (unsigned)std::max<long>(b, kXcds);
   }
   template <typename S>
-  static void fused(const DevCode& cd, int Fmax, const float* prior, const S* cin, S* cout, uint8_t* hard,
-                    uint8_t* fsw, const int* alist, const int* nact, int first, int decide, int write,
-                    int cap, hipStream_t s, const int* ell_p = nullptr, int max_iter = 0) {
+  static void fused(const DevCode& cd, int Fmax, const float* prior, S* buf0, S* buf1, uint8_t* hard, uint8_t* fsw,
+                    const int* alist, const int* nact, const int* rnd, const int* maxit, int maxit_all, int cap,
+                    hipStream_t s) {
     if (Fmax == 0) return;
     hipLaunchKernelGGL((k_fused<G, KMAX, S>), dim3(fused_blocks(cd, Fmax, cap)), dim3(64 * kWaves), lds(), s, cd,
-                       prior, cin, cout, hard, fsw, alist, nact, first, decide, write, ell_p, max_iter);
+                       prior, buf0, buf1, hard, fsw, alist, nact, rnd, maxit, maxit_all);
   }
 };
 
@@ -187,7 +187,7 @@ struct FusedWs {
   uint32_t* unsat;
   uint32_t* mism;
   int* nact;
-  int* ell;
+  int* rnd;  // [F] per-frame round
 };
 
 size_t plain_layout(const ldpc_fd_code_s* c, int F, char* base, PlainWs* w) {
@@ -218,7 +218,7 @@ size_t fused_layout(const ldpc_fd_code_s* c, int F, int prec, char* base, FusedW
   char* p5 = take((size_t)F * 4);
   char* p6 = take((size_t)F * 4);
   char* p7 = take(4);
-  char* p8 = take(4);
+  char* p8 = take((size_t)F * 4);
   if (w)
     *w = FusedWs{(float*)pt, {b0, b1}, (uint8_t*)p2, (int*)p3, (int*)p4, (uint32_t*)p5, (uint32_t*)p6, (int*)p7, (int*)p8};
   return off;
@@ -247,14 +247,14 @@ void launch_prior(const ldpc_fd_code_s* c, int F, const float* llr, float* prior
 // F frames gated by `active`).
 void launch_syndrome(const ldpc_fd_code_s* c, int F, const uint8_t* hard, const uint8_t* fsw, uint8_t* synd,
                      uint8_t* fsynd, uint32_t* unsat, uint32_t* mism, const int* alist, const int* nact,
-                     const uint32_t* active, hipStream_t s) {
+                     const uint32_t* active, hipStream_t s, const int* rnd = nullptr) {
   const size_t lds = 4 * (size_t)(((c->N + 3) >> 2) + ((c->E + 3) >> 2));
   if (lds <= 60000) {
     hipLaunchKernelGGL(k_syndrome_frames, dim3((unsigned)std::min(F, 4096)), dim3(256), lds, s, c->dev, hard, fsw,
-                       synd, fsynd, unsat, mism, alist, nact, F, active);
+                       synd, fsynd, unsat, mism, alist, nact, F, active, rnd);
   } else {
     hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, c->dev, hard, fsw, synd,
-                       fsynd, unsat, mism, alist, nact, F, active);
+                       fsynd, unsat, mism, alist, nact, F, active, rnd);
   }
 }
 
@@ -440,7 +440,7 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
     PlainWs w;
     plain_layout(c, F, (char*)workspace, &w);
     hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, w.active, w.unsat, w.mism, (int*)nullptr,
-                       (int*)nullptr, iters, status, (int*)nullptr);
+                       (int*)nullptr, iters, status, (int*)nullptr, 0);
     bool ok = dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
       using I = decltype(impl);
       timed(LDPC_FD_K_VAR, s, [&] { I::var_plain(cd, F, llr, nullptr, w.v2c, hard, w.fsw, w.active, 1, s); });
@@ -467,47 +467,45 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
   FusedWs w;
   fused_layout(c, F, prec, (char*)workspace, &w);
   hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, (uint32_t*)nullptr, w.unsat, w.mism, w.alist,
-                     w.nact, iters, status, w.ell);
+                     w.nact, iters, status, w.rnd, 0);
   launch_prior(c, F, llr, w.prior, s);
-  auto run_pass = [&](int first, int decide, int write, const void* cin, void* cout, hipStream_t st) {
-    return dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
+  // One pass over the active frames (each at its own round, see k_fused),
+  // syndromes of the decisions it formed, stopping rule and compaction.
+  auto enqueue_round = [&](hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    bool ok = true;
+    if (e0) (void)hipEventRecord(e0, st);
+    ok = dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
       using I = decltype(impl);
       if (prec == LDPC_FD_FP32)
-        I::template fused<float>(cd, F, w.prior, (const float*)cin, (float*)cout, hard, w.fsw, w.alist, w.nact, first,
-                                 decide, write, c->blocks, st, w.ell, max_iter);
+        I::template fused<float>(cd, F, w.prior, (float*)w.buf[0], (float*)w.buf[1], hard, w.fsw, w.alist, w.nact,
+                                 w.rnd, nullptr, max_iter, c->blocks, st);
       else if (prec == LDPC_FD_FP16)
-        I::template fused<_Float16>(cd, F, w.prior, (const _Float16*)cin, (_Float16*)cout, hard, w.fsw, w.alist,
-                                    w.nact, first, decide, write, c->blocks, st, w.ell, max_iter);
+        I::template fused<_Float16>(cd, F, w.prior, (_Float16*)w.buf[0], (_Float16*)w.buf[1], hard, w.fsw, w.alist,
+                                    w.nact, w.rnd, nullptr, max_iter, c->blocks, st);
       else
-        I::template fused<bf16_t>(cd, F, w.prior, (const bf16_t*)cin, (bf16_t*)cout, hard, w.fsw, w.alist, w.nact,
-                                  first, decide, write, c->blocks, st, w.ell, max_iter);
+        I::template fused<bf16_t>(cd, F, w.prior, (bf16_t*)w.buf[0], (bf16_t*)w.buf[1], hard, w.fsw, w.alist,
+                                  w.nact, w.rnd, nullptr, max_iter, c->blocks, st);
     });
-  };
-  // One round l (l read from device memory): fused pass l -> l+1 with the
-  // decision of round l, syndromes, stopping rule and compaction.
-  auto enqueue_round = [&](int ell_parity, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    if (e0) (void)hipEventRecord(e0, st);
-    run_pass(0, 1, -1, w.buf[ell_parity & 1], w.buf[(ell_parity + 1) & 1], st);
     if (e1) (void)hipEventRecord(e1, st);
-    launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, w.alist, w.nact, nullptr, st);
-    hipLaunchKernelGGL(k_retire_compact, dim3(1), dim3(1024), 0, st, 0, max_iter, w.alist, w.tmp, w.nact, w.unsat,
-                       w.mism, iters, status, w.ell);
+    launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, w.alist, w.nact, nullptr, st, w.rnd);
+    hipLaunchKernelGGL(k_retire_compact, dim3(1), dim3(1024), 0, st, max_iter, (const int*)nullptr, w.alist, w.tmp,
+                       w.nact, w.unsat, w.mism, iters, status, w.rnd, (int*)nullptr, (int*)nullptr);
+    return ok;
   };
-  bool ok = true;
-  timed(LDPC_FD_K_FUSED, s, [&] { ok = run_pass(1, 0, 1, nullptr, w.buf[1], s); });
-  if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+  // A frame needs at most max_iter + 1 passes (pass l forms round l's decision).
+  const int passes = max_iter + 1;
   // Kernel timing needs per-launch events, which HIP cannot time inside a
-  // replayed graph: profiled decodes launch every round from the host.
+  // replayed graph: profiled decodes launch every pass from the host.
   if (!c->graphs || t_prof.on) {
-    for (int ell = 1; ell <= max_iter; ++ell) {
+    for (int p = 1; p <= passes; ++p) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (t_prof.on) {
         e0 = t_prof.get();
         e1 = t_prof.get();
         if (e0 && e1) t_prof.ev[LDPC_FD_K_FUSED].emplace_back(e0, e1);
       }
-      enqueue_round(ell, s, e0, e1);
-      if (ell % c->chunk == 0 || ell == max_iter) {
+      if (!enqueue_round(s, e0, e1)) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+      if (p % c->chunk == 0 || p == passes) {
         int left = 0;
         if ((rc = read_count(w.nact, s, &left))) return rc;
         if (left == 0) break;
@@ -516,10 +514,9 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
     HIP_TRY(hipGetLastError());
     return LDPC_FD_OK;
   }
-  // Replay captured chunks of `chunk` rounds (even, so that chunk k always
-  // starts on the same ping-pong buffer).  Rounds past max_iter in the last
-  // chunk find no active frame and do nothing.
-  const int chunk = (c->chunk + 1) & ~1;
+  // Replay a captured chunk of passes; passes after every frame has stopped
+  // find an empty active list and do nothing.
+  const int chunk = c->chunk;
   ldpc_fd_code_s::GraphKey key{F, prec, chunk, max_iter, c->logr, c->blocks, 0,
                                workspace, llr, hard, synd, iters, status};
   std::lock_guard<std::mutex> lock(c->gmu);
@@ -532,15 +529,20 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
     ldpc_fd_code_s::GraphEntry g{key, nullptr, {}};
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int r = 0; r < chunk; ++r) enqueue_round(1 + r, c->cap_stream, nullptr, nullptr);
+    bool ok = true;
+    for (int r = 0; r < chunk; ++r) ok = enqueue_round(c->cap_stream, nullptr, nullptr) && ok;
     HIP_TRY(hipStreamEndCapture(c->cap_stream, &graph));
+    if (!ok) {
+      (void)hipGraphDestroy(graph);
+      return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+    }
     hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) return fail(LDPC_FD_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
     c->gcache.push_back(g);
     ge = &c->gcache.back();
   }
-  for (int ell0 = 1; ell0 <= max_iter; ell0 += chunk) {
+  for (int p = 0; p < passes; p += chunk) {
     HIP_TRY(hipGraphLaunch(ge->exec, s));
     int left = 0;
     if ((rc = read_count(w.nact, s, &left))) return rc;
@@ -570,10 +572,11 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   const size_t n_msg = (size_t)F * c->E * c->q;
   const size_t n_st = prec == LDPC_FD_FP32 ? 0 : align256(n_msg * 2);
   const size_t n_pr = align256((size_t)F * c->N * c->m * 4);
-  HIP_TRY(hipMalloc((void**)&tmp, n_fsw + 4 * n4 + 256 + 2 * n_st + n_pr));
+  HIP_TRY(hipMalloc((void**)&tmp, n_fsw + 4 * n4 + 256 + 2 * n_st + n_pr + n4));
   char* st_in = tmp + n_fsw + 4 * n4 + 256;
   char* st_out = st_in + n_st;
   float* prior = (float*)(st_out + n_st);
+  int* rnd = (int*)(tmp + n_fsw + 4 * n4 + 256 + 2 * n_st + n_pr);
   uint8_t* fsw = (uint8_t*)tmp;
   uint32_t* active = (uint32_t*)(tmp + n_fsw);
   uint32_t* unsat = (uint32_t*)(tmp + n_fsw + n4);
@@ -582,7 +585,7 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   int* nact = (int*)(tmp + n_fsw + 4 * n4);
   const unsigned fb = cdiv(F, 256);
   hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, active, unsat, mism, alist, nact, (int32_t*)nullptr,
-                     (uint32_t*)nullptr, (int*)nullptr);
+                     (uint32_t*)nullptr, rnd, c2v_in ? 1 : 0);
   launch_prior(c, F, llr, prior, s);
   bool ok = dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
     using I = decltype(impl);
@@ -590,22 +593,31 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
       I::var_plain(cd, F, llr, c2v_in, v2c_out, hard, fsw, nullptr, c2v_in ? 0 : 1, s);
       if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
       I::check_plain(cd, F, v2c_out, c2v_out, nullptr, s);
-    } else if (prec == LDPC_FD_FP32) {
-      I::template fused<float>(cd, F, prior, c2v_in, c2v_out, hard, fsw, alist, nact, c2v_in ? 0 : 1,
-                               c2v_in ? 1 : 0, 1, c->blocks, s);
-      if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, alist, nact, nullptr, s);
     } else {
-      // round the imported state to the storage type, run the pass on it, widen the result
+      // Frames at round 1 read buffer 1 and write buffer 0; frames at round 0
+      // (no imported state) write buffer 1.  16-bit storage: the imported state
+      // is rounded to the storage type first and the result widened back.
       auto run = [&](auto tag) {
         using S = decltype(tag);
+        S* in = (S*)c2v_in;
+        S* out = (S*)c2v_out;
         const unsigned g = (unsigned)std::min<size_t>((n_msg / 4 + 255) / 256, 65536);
-        if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, (S*)st_in, n_msg / 4);
-        I::template fused<S>(cd, F, prior, c2v_in ? (const S*)st_in : nullptr, (S*)st_out, hard, fsw, alist, nact,
-                             c2v_in ? 0 : 1, c2v_in ? 1 : 0, 1, c->blocks, s);
-        hipLaunchKernelGGL((k_convert<S, float>), dim3(g), dim3(256), 0, s, (const S*)st_out, c2v_out, n_msg / 4);
+        if (prec != LDPC_FD_FP32) {
+          in = (S*)st_in;
+          out = (S*)st_out;
+          if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, in, n_msg / 4);
+        }
+        if (c2v_in)
+          I::template fused<S>(cd, F, prior, out, in, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, s);
+        else
+          I::template fused<S>(cd, F, prior, nullptr, out, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, s);
+        if (prec != LDPC_FD_FP32)
+          hipLaunchKernelGGL((k_convert<S, float>), dim3(g), dim3(256), 0, s, (const S*)out, c2v_out, n_msg / 4);
       };
-      if (prec == LDPC_FD_FP16) run(_Float16{}); else run(bf16_t{});
-      if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, alist, nact, nullptr, s);
+      if (prec == LDPC_FD_FP32) run(float{});
+      else if (prec == LDPC_FD_FP16) run(_Float16{});
+      else run(bf16_t{});
+      if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, alist, nact, nullptr, s, rnd);
     }
   });
   hipError_t e1 = hipStreamSynchronize(s);

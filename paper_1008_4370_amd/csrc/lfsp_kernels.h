@@ -223,8 +223,30 @@ __global__ __launch_bounds__(256) void k_check_plain(DevCode cd, int F, const fl
 //   first:   round 0 -> 1 (Lambda_vc = Lambda^(0), no decision).
 //   decide:  form the decision of round l.
 //   write:   store round l+1 (off in the last pass).
+// Per-frame round state of the fused decoder.  rnd[f] = l is the number of
+// check-to-variable rounds computed for frame f; C2V^(l) lives in buffer l & 1.
+// A pass on frame f reads C2V^(l) (nothing when l = 0: the variable-to-check
+// messages are then Lambda^(0)), forms the tentative decision of round l
+// (l >= 1) and writes C2V^(l+1) into buffer (l+1) & 1 unless l has reached the
+// frame's max_iter.  Frames at different rounds share a pass.
+struct FrameState {
+  bool first, decide, write;
+  int ell;
+};
+
+__device__ __forceinline__ FrameState frame_state(const int* __restrict__ rnd, const int* __restrict__ maxit,
+                                                  int maxit_all, int f) {
+  FrameState st;
+  st.ell = rnd[f];
+  const int mi = maxit ? maxit[f] : maxit_all;
+  st.first = st.ell == 0;
+  st.decide = st.ell >= 1;
+  st.write = st.ell < mi;
+  return st;
+}
+
 // Loads of one edge: the other edge's message, the own message (owner visits
-// of a deciding pass) and the LLRs of the variable.
+// of a deciding pass) and the prior factors of the variable.
 template <class G, typename S>
 struct EdgeLoads {
   float x[G::R];
@@ -234,38 +256,41 @@ struct EdgeLoads {
 
 template <class G, typename S>
 __device__ __forceinline__ void issue_edge(const DevCode& cd, const float* __restrict__ tp, const S* __restrict__ cin,
-                                           size_t fb, int f, int e, int first, int decide_flag, int zl,
+                                           size_t fb, int f, int e, const FrameState& fs, bool any_decide, int zl,
                                            EdgeLoads<G, S>& L) {
   const int v = uni(cd.e_var[e]);
   const int eo = uni(cd.e_other[e]);
   const float* lp = tp + ((size_t)f * cd.N + v) * G::LOGQ;
 #pragma unroll
   for (int i = 0; i < G::LOGQ; ++i) L.l[i] = lp[i];
-  if (!first) load_msg<G, S>(cin + fb + (size_t)eo * G::Q, zl, L.x);
-  if (decide_flag && e < eo) load_msg<G, S>(cin + fb + (size_t)e * G::Q, zl, L.o);
+  if (!fs.first) load_msg<G, S>(cin + fb + (size_t)eo * G::Q, zl, L.x);
+  if (any_decide && e < eo && fs.decide) load_msg<G, S>(cin + fb + (size_t)e * G::Q, zl, L.o);
 }
 
 template <class G, int KMAX, typename S>
-__device__ __forceinline__ void fused_item(const DevCode& cd, const float* __restrict__ tp,
-                                           const S* __restrict__ cin, S* __restrict__ cout,
-                                           uint8_t* __restrict__ hard, uint8_t* __restrict__ fsw, int f,
-                                           bool valid, int c, float* lds, int rb, int cf, int zl, int first,
-                                           int decide_flag, int write) {
+__device__ __forceinline__ void fused_item(const DevCode& cd, const float* __restrict__ tp, S* __restrict__ buf0,
+                                           S* __restrict__ buf1, uint8_t* __restrict__ hard,
+                                           uint8_t* __restrict__ fsw, int f, bool valid, const FrameState& fs,
+                                           int c, float* lds, int rb, int cf, int zl) {
   const int e0 = uni(cd.row_ptr[c]), deg = uni(cd.row_ptr[c + 1]) - e0;
   const size_t fb = (size_t)f * cd.E * G::Q;
+  const S* cin = (fs.ell & 1) ? buf1 : buf0;
+  S* cout = (fs.ell & 1) ? buf0 : buf1;
+  const bool any_decide = __builtin_amdgcn_ballot_w64(fs.decide && valid) != 0;
+  const bool any_write = __builtin_amdgcn_ballot_w64(fs.write && valid) != 0;
   float st[KMAX][G::R];   // Lambda~_vc of each edge (check coordinates)
   float smag[G::R];
 #pragma unroll
   for (int r = 0; r < G::R; ++r) smag[r] = 0.0f;
   // edge j+1's loads are in flight while edge j is computed
   EdgeLoads<G, S> nxt;
-  issue_edge<G, S>(cd, tp, cin, fb, f, e0, first, decide_flag, zl, nxt);
+  issue_edge<G, S>(cd, tp, cin, fb, f, e0, fs, any_decide, zl, nxt);
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j < deg) {
       const int e = e0 + j;
       const EdgeLoads<G, S> cur = nxt;
-      if (j + 1 < deg) issue_edge<G, S>(cd, tp, cin, fb, f, e + 1, first, decide_flag, zl, nxt);
+      if (j + 1 < deg) issue_edge<G, S>(cd, tp, cin, fb, f, e + 1, fs, any_decide, zl, nxt);
       const int v = uni(cd.e_var[e]);
       const int eo = uni(cd.e_other[e]);
       const int h = uni(cd.e_label[e]);
@@ -274,16 +299,16 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
       for (int i = 0; i < G::LOGQ; ++i) t[i] = cur.l[i];   // prior factors tanh(L_i / 2)
 #pragma unroll
       for (int r = 0; r < G::R; ++r)
-        st[j][r] = first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
+        st[j][r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
       conv_prior<G>(st[j], t);
-      if (decide_flag && e < eo) {
+      if (any_decide && e < eo) {
         float xo[G::R];
 #pragma unroll
         for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
         int hd, fa, fo;
         const int ho = uni(cd.e_label[eo]);
         decide<G>(st[j], xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
-        if (valid && zl == 0) {
+        if (valid && fs.decide && zl == 0) {
           hard[(size_t)f * cd.N + v] = (uint8_t)hd;
           fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
           fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
@@ -295,7 +320,7 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
       for (int r = 0; r < G::R; ++r) smag[r] += __builtin_fabsf(st[j][r]);
     }
   }
-  if (!write) return;
+  if (!any_write) return;
   // GF(2) sign of the full sum (XOR over the check's edges)
   uint32_t ssgn[G::R];
 #pragma unroll
@@ -318,7 +343,7 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
         o[r] = __uint_as_float(((ssgn[r] ^ __float_as_uint(st[j][r])) & 0x80000000u) | __float_as_uint(mag));
       }
       permute<G>(o, lds, rb, cf, zl, uni64(cd.colsT[hinv]));
-      if (valid) store_msg<G, S>(cout + fb + (size_t)e * G::Q, zl, o);
+      if (valid && fs.write) store_msg<G, S>(cout + fb + (size_t)e * G::Q, zl, o);
     }
   }
 }
@@ -331,15 +356,12 @@ constexpr int kXcds = 8;
 // other edge of its variable, and by its own check at the owner visit) come
 // from the same XCD's L2.  gridDim.x must be a multiple of 8.
 template <class G, int KMAX, typename S>
-__global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restrict__ tp,
-                                               const S* __restrict__ cin, S* __restrict__ cout,
-                                               uint8_t* __restrict__ hard, uint8_t* __restrict__ fsw,
-                                               const int* __restrict__ alist, const int* __restrict__ nact_p,
-                                               int first, int decide_flag, int write, const int* __restrict__ ell_p,
-                                               int max_iter) {
+__global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restrict__ tp, S* __restrict__ buf0,
+                                               S* __restrict__ buf1, uint8_t* __restrict__ hard,
+                                               uint8_t* __restrict__ fsw, const int* __restrict__ alist,
+                                               const int* __restrict__ nact_p, const int* __restrict__ rnd,
+                                               const int* __restrict__ maxit, int maxit_all) {
   extern __shared__ float lds[];
-  // write < 0: store round l+1 unless the device round counter l has reached max_iter
-  if (write < 0) write = *ell_p < max_iter;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int waves = blockDim.x >> 6;
   const int nact = *nact_p;
@@ -356,7 +378,8 @@ __global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restri
     const int slot = g * G::T + fl;
     const bool valid = slot < nact;
     const int f = alist[valid ? slot : nact - 1];
-    fused_item<G, KMAX, S>(cd, tp, cin, cout, hard, fsw, f, valid, c, lds, rb, cf, zl, first, decide_flag, write);
+    const FrameState fs = frame_state(rnd, maxit, maxit_all, f);
+    fused_item<G, KMAX, S>(cd, tp, buf0, buf1, hard, fsw, f, valid, fs, c, lds, rb, cf, zl);
   }
 }
 
@@ -368,13 +391,14 @@ __global__ void k_syndrome(DevCode cd, const uint8_t* __restrict__ hard, const u
                            uint8_t* __restrict__ synd, uint8_t* __restrict__ fsynd,
                            uint32_t* __restrict__ unsat, uint32_t* __restrict__ mism,
                            const int* __restrict__ alist, const int* __restrict__ nact_p, int F_all,
-                           const uint32_t* __restrict__ active) {
+                           const uint32_t* __restrict__ active, const int* __restrict__ rnd) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int nact = nact_p ? *nact_p : F_all;
   if (i >= (long)nact * cd.M) return;
   const int slot = (int)(i / cd.M), c = (int)(i % cd.M);
   const int f = alist ? alist[slot] : slot;
   if (active && !active[f]) return;
+  if (rnd && rnd[f] == 0) return;
   const int e0 = cd.row_ptr[c], e1 = cd.row_ptr[c + 1];
   int s = 0, sf = 0;
   for (int e = e0; e < e1; ++e) {
@@ -414,7 +438,8 @@ __global__ __launch_bounds__(256) void k_syndrome_frames(DevCode cd, const uint8
                                                          uint32_t* __restrict__ unsat, uint32_t* __restrict__ mism,
                                                          const int* __restrict__ alist,
                                                          const int* __restrict__ nact_p, int F_all,
-                                                         const uint32_t* __restrict__ active) {
+                                                         const uint32_t* __restrict__ active,
+                                                         const int* __restrict__ rnd) {
   extern __shared__ uint32_t smw[];
   uint8_t* sh = reinterpret_cast<uint8_t*>(smw);   // [N] (rounded up to words)
   const int nw = (cd.N + 3) >> 2, ew = (cd.E + 3) >> 2;
@@ -428,6 +453,7 @@ __global__ __launch_bounds__(256) void k_syndrome_frames(DevCode cd, const uint8
   for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
     const int f = alist ? alist[slot] : slot;
     if (active && !active[f]) continue;  // uniform over the block
+    if (rnd && rnd[f] == 0) continue;     // fresh frame: no decision this pass
     if (wN) {
       const uint32_t* src = reinterpret_cast<const uint32_t*>(hard + (size_t)f * cd.N);
       for (int i = threadIdx.x; i < nw; i += blockDim.x) smw[i] = src[i];
@@ -476,11 +502,11 @@ __global__ void k_convert(const Sin* __restrict__ in, Sout* __restrict__ out, si
 }
 
 __global__ void k_init_frames(int F, uint32_t* active, uint32_t* unsat, uint32_t* mism, int* alist,
-                              int* nact, int32_t* iters, uint32_t* status, int* ell) {
+                              int* nact, int32_t* iters, uint32_t* status, int* rnd, int rnd0) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f == 0 && nact) *nact = F;
-  if (f == 0 && ell) *ell = 1;
   if (f >= F) return;
+  if (rnd) rnd[f] = rnd0;
   if (active) active[f] = 1u;
   unsat[f] = 0u;
   mism[f] = 0u;
@@ -509,33 +535,44 @@ __global__ void k_retire_plain(int F, int ell, int max_iter, uint32_t* active, u
   mism[f] = 0u;
 }
 
-// FUSED decoder: stopping rule for round ell and stable compaction of the
-// active list (single workgroup of 1024 threads).
-// With ell_p set, the round number is read from (and then advanced in) device
-// memory, so that a captured chunk of rounds replays unchanged.
-__global__ __launch_bounds__(1024) void k_retire_compact(int ell, int max_iter, int* alist, int* tmp,
-                                                         int* nact_p, uint32_t* unsat, uint32_t* mism,
-                                                         int32_t* iters, uint32_t* status, int* ell_p) {
+// FUSED decoder: stopping rule and stable compaction of the active list (single
+// workgroup of 1024 threads).  For each active frame with l = rnd[f] >= 1 the
+// decision of round l was formed in the pass: iters = l; the frame stops when
+// both syndromes were zero, or fails at l = max_iter.  Continuing frames
+// advance rnd.  Stopped frames are appended to `done` (when given) for
+// harvesting.
+__global__ __launch_bounds__(1024) void k_retire_compact(int maxit_all, const int* __restrict__ maxit, int* alist,
+                                                         int* tmp, int* nact_p, uint32_t* unsat, uint32_t* mism,
+                                                         int32_t* iters, uint32_t* status, int* rnd, int* done,
+                                                         int* ndone) {
   __shared__ int wsum[16];
   __shared__ int base_s;
-  if (ell_p) ell = *ell_p;
   const int nact = *nact_p;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid == 0) base_s = 0;
   __syncthreads();
   for (int start = 0; start < nact; start += 1024) {
     const int i = start + tid;
-    int keep = 0, f = -1;
+    int keep = 0, f = -1, stop = 0;
     if (i < nact) {
       f = alist[i];
-      iters[f] = ell;
-      uint32_t st = status[f] | (mism[f] ? 2u : 0u);
-      if (!unsat[f]) st |= 1u;
-      else if (ell < max_iter) keep = 1;
-      status[f] = st;
-      unsat[f] = 0u;
-      mism[f] = 0u;
+      const int ell = rnd[f];
+      if (ell >= 1) {
+        iters[f] = ell;
+        uint32_t st = status[f] | (mism[f] ? 2u : 0u);
+        const bool conv = !unsat[f];
+        if (conv) st |= 1u;
+        status[f] = st;
+        unsat[f] = 0u;
+        mism[f] = 0u;
+        keep = !conv && ell < (maxit ? maxit[f] : maxit_all);
+      } else {
+        keep = 1;
+      }
+      if (keep) rnd[f] = ell + 1;
+      stop = !keep;
     }
+    if (done && stop) done[atomicAdd(ndone, 1)] = f;
     const uint64_t b = __builtin_amdgcn_ballot_w64(keep);
     const int pre = __builtin_popcountll(b & ((1ull << lane) - 1ull));
     if (lane == 0) wsum[w] = __builtin_popcountll(b);
@@ -545,19 +582,16 @@ __global__ __launch_bounds__(1024) void k_retire_compact(int ell, int max_iter, 
     if (keep) tmp[off + pre] = f;
     __syncthreads();
     if (tid == 0) {
-      int s = 0;
-      for (int k = 0; k < 16; ++k) s += wsum[k];
-      base_s += s;
+      int s2 = 0;
+      for (int k = 0; k < 16; ++k) s2 += wsum[k];
+      base_s += s2;
     }
     __syncthreads();
   }
   const int total = base_s;
   for (int i = tid; i < total; i += 1024) alist[i] = tmp[i];
   __syncthreads();
-  if (tid == 0) {
-    *nact_p = total;
-    if (ell_p) *ell_p = ell + 1;
-  }
+  if (tid == 0) *nact_p = total;
 }
 
 }  // namespace ldpcfd
