@@ -69,14 +69,110 @@ def alg_bytes(code, iters, s, first_pass=True):
     return int(len(iters) * first + int(np.sum(iters)) * per_round)
 
 
+C4_MIX = ("gf16_n2048", "gf64_n512", "gf256_n256_k16")
+C5_LOADS = (20000, 50000, 100000, 150000, 200000)
+
+
+def run_mixed(args):
+    """Uneven multi-code batch: 3000 GF(16) N=2048, 6000 GF(64) N=512 and 2000
+    GF(256) k=16 N=256 frames at 2.5 dB decoded together (one graph replay per
+    chunk of passes runs all three codes on concurrent streams), against the
+    same three batches decoded one after the other."""
+    import torch
+    from paper_1008_4370_amd import autotune, serving, synth
+    from paper_1008_4370_amd import decoder as D
+    batches = [synth.make_batch(w) for w in C4_MIX]
+    codes = [D.Code.from_synth(b.code) for b in batches]
+    tuned = [autotune.apply(c, args.prec, b.llr.shape[0]) is not None for c, b in zip(codes, batches)]
+    llrs = [torch.from_numpy(b.llr).cuda() for b in batches]
+    pool = D.Pool(codes, [b.llr.shape[0] for b in batches], prec=args.prec)
+    chunk = args.chunk or 4
+    for _ in range(args.warmup):
+        serving.decode_mixed(pool, llrs, args.max_iter, chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = serving.decode_mixed(pool, llrs, args.max_iter, chunk)
+    torch.cuda.synchronize()
+    ms_mix = (time.perf_counter() - t0) / args.steps * 1e3
+    pool.close()
+    # the same batches, one code after the other
+    decs = [D.Decoder(c, b.llr.shape[0], args.prec, "fused") for c, b in zip(codes, batches)]
+    for d, l in zip(decs, llrs):
+        d(l, args.max_iter)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for d, l in zip(decs, llrs):
+            d(l, args.max_iter)
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) / args.steps * 1e3
+    bits = sum(b.llr.shape[0] * b.info_bits_per_frame for b in batches)
+    per_code = []
+    for b, r, t in zip(batches, res, tuned):
+        per_code.append({"code": f"GF({b.code.q}) k={int(round(2 * b.code.N / b.code.M))} N={b.code.N}",
+                         "frames": int(b.llr.shape[0]), "fer": float(np.any(r["hard"] != b.cw, axis=1).mean()),
+                         "mean_iters": float(r["iters"].mean()), "autotuned": t})
+    line = {
+        "metric": "decoded Mbit/s, uneven multi-code batch (3 codes, 11000 frames)",
+        "value": round(bits / (ms_mix / 1e3) / 1e6, 3), "unit": "Mbit/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_mix, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3000 x GF(16)(2,4) N=2048 + 6000 x GF(64)(2,6) N=512 + 2000 x GF(256)(2,16) "
+                               f"N=256, 2.5 dB, max {args.max_iter} rounds, one pool, {chunk} passes per replay",
+                   "storage": args.prec, "parallelism": "1 GPU"},
+        "sequential_ms_per_step": round(ms_seq, 4),
+        "sequential_mbps": round(bits / (ms_seq / 1e3) / 1e6, 3),
+        "per_code": per_code, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_serving(args):
+    """Poisson-arriving requests (32 frames, one of the three mixed-batch codes
+    each, Eb/N0 uniform over 2.0..3.5 dB) at several offered loads."""
+    from paper_1008_4370_amd import serving, synth
+    specs = []
+    for w in C4_MIX:
+        d = synth.WORKLOADS[w]
+        specs.append((d["m"], d["k"], d["N"]))
+    banks = serving.make_banks(specs, snr_range=(2.0, 3.5), snr_points=16, frames_per_point=256)
+    prec = args.prec
+    sweep = []
+    for load in C5_LOADS:
+        r = serving.serve(banks, load, args.serve_seconds, prec=prec, max_iter=args.max_iter, request_frames=32,
+                          hbm_budget=8 << 30)
+        print(f"[bench] offered {load} frames/s: achieved {r['achieved_fps']:.0f}, "
+              f"p50 {r['frame_latency_ms']['p50']:.2f} ms p99 {r['frame_latency_ms']['p99']:.2f} ms",
+              file=sys.stderr, flush=True)
+        sweep.append({k: r[k] for k in ("offered_fps", "achieved_fps", "info_mbps", "frame_latency_ms",
+                                        "request_latency_ms", "frames", "fer", "slots")})
+    best = max(sweep, key=lambda x: x["info_mbps"])
+    line = {
+        "metric": "serving Mbit/s and p50/p99 frame latency vs offered load (3 codes, Poisson arrivals)",
+        "value": round(best["info_mbps"], 3), "unit": "Mbit/s", "n_gpus": 1, "steps": len(sweep), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "requests of 32 frames, uniform over GF(16)(2,4) N=2048, GF(64)(2,6) N=512, "
+                               "GF(256)(2,16) N=256; Eb/N0 per request uniform over 16 points in [2.0, 3.5] dB; "
+                               f"max {args.max_iter} rounds; 8 GiB of frame slots",
+                   "storage": prec, "seconds_per_load": args.serve_seconds, "parallelism": "1 GPU"},
+        "sweep": sweep, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="gf64_n1000")
+    ap.add_argument("--workload", default="gf64_n1000",
+                    help="a synthetic workload name, or 'mixed' (three codes in one pool) or 'serving' "
+                         "(Poisson arrivals over the three codes at several loads)")
     ap.add_argument("--point", type=int, default=2, help="Eb/N0 index (gf64_n1000: 2 -> 2.5 dB)")
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--prec", default=None, choices=["fp32", "fp16", "bf16"],
+                    help="message storage (default fp32; fp16 for the serving workload)")
     ap.add_argument("--mode", default="fused", choices=["fused", "plain"])
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -88,6 +184,9 @@ def main():
                     help="time steps without per-kernel HIP events (lets the decoder replay graphs); "
                          "roofline is then omitted")
     ap.add_argument("--graphs", type=int, default=-1, help="1/0: replay captured round chunks (-1 = default)")
+    ap.add_argument("--serve-load", type=float, default=100000.0,
+                    help="offered frames/s of the serving phase that measures p50/p99 frame latency (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (calibrates rocprofv3 "
                          "FETCH_SIZE/WRITE_SIZE against a known byte count) and exit")
@@ -104,9 +203,15 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "frames would shard across GPUs with no per-round exchange (see DESIGN.md).", file=sys.stderr)
+              "frames would shard across GPUs with no per-round exchange.", file=sys.stderr)
         sys.exit(2)
 
+    if args.prec is None:
+        args.prec = "fp16" if args.workload == "serving" else "fp32"
+    if args.workload == "mixed":
+        return run_mixed(args)
+    if args.workload == "serving":
+        return run_serving(args)
     from paper_1008_4370_amd import synth
     batch = synth.make_batch(args.workload, point=args.point)
     F = batch.llr.shape[0]
@@ -119,6 +224,8 @@ def main():
     import torch
     from paper_1008_4370_amd import decoder as D
     code = D.Code.from_synth(batch.code)
+    from paper_1008_4370_amd import autotune
+    tuned = autotune.apply(code, args.prec, F) is not None
     tune = {k: v for k, v in (("lane_entries", args.lane_entries), ("grid_blocks", args.grid_blocks),
                               ("chunk", args.chunk)) if v}
     if args.graphs >= 0:
@@ -143,6 +250,20 @@ def main():
     kms, launches = D.profile_read(kernel)
     ms_var, launches_var = D.profile_read(D.K_VAR)
     ms_step = (t1 - t0) / args.steps * 1e3
+
+    serve = None
+    if args.serve_load > 0:
+        # Continuous batching of the same frames arriving as a Poisson process
+        # (requests of 32 frames), same storage precision; latency is arrival
+        # to harvest on the host.
+        from paper_1008_4370_amd import serving
+        bank = serving.bank_from_batch(batch, code)
+        budget = 1024 * serving.D.pool_slot_bytes(code, args.prec)   # 1024 frame slots
+        serve = serving.serve([bank], args.serve_load, args.serve_seconds, prec=args.prec, max_iter=args.max_iter,
+                              request_frames=32, hbm_budget=budget, warmup_s=0.5)
+        print(f"[bench] serving at {args.serve_load:.0f} frames/s: {serve['achieved_fps']:.0f} frames/s, "
+              f"p50 {serve['frame_latency_ms']['p50']:.2f} ms, p99 {serve['frame_latency_ms']['p99']:.2f} ms",
+              file=sys.stderr, flush=True)
 
     hard = out["hard"].cpu().numpy()
     iters = out["iters"].cpu().numpy()
@@ -187,6 +308,7 @@ def main():
             "info_bits_per_frame": info_bits,
             "parallelism": "1 GPU",
             "tuning": code.get_tuning(),
+            "autotuned": tuned and not tune,
         },
         "roofline": None if achieved is None else {
             "bound": "hbm",
@@ -205,8 +327,17 @@ def main():
         "mean_iters": float(iters.mean()),
         "max_iters": int(iters.max()),
         "converged": float(((status & 1) != 0).mean()),
-        "latency_ms": {"p50": round(ms_step, 4), "p99": round(ms_step, 4),
-                       "note": "batch mode: every frame's result is returned with the batch"},
+        "latency_ms": None if serve is None else {
+            "p50": round(serve["frame_latency_ms"]["p50"], 3),
+            "p99": round(serve["frame_latency_ms"]["p99"], 3),
+            "request_p50": round(serve["request_latency_ms"]["p50"], 3),
+            "request_p99": round(serve["request_latency_ms"]["p99"], 3),
+            "offered_fps": args.serve_load,
+            "achieved_fps": round(serve["achieved_fps"], 1),
+            "serving_mbps": round(serve["info_mbps"], 3),
+            "slots": serve["slots"][0],
+            "note": "frame arrival (Poisson, requests of 32 frames) to harvest, continuous batching",
+        },
     }
     print(json.dumps(line), flush=True)
 

@@ -142,6 +142,57 @@ int32_t ldpc_fd_round(ldpc_fd_code code, int32_t frames, const float *llr, const
                       float *v2c_out, float *c2v_out, uint8_t *hard, uint8_t *fsynd,
                       uint8_t *synd, int32_t mode, int32_t prec, void *stream);
 
+/* ---- Decoding pool: continuous batching over several codes -------------------
+ * A pool owns, for each of its codes, `slots[k]` frame slots in device memory
+ * (message state, decisions and per-frame round counter; ldpc_fd_pool_slot_bytes
+ * gives the bytes per slot, for admission against an HBM budget).  Frames are
+ * admitted into free slots at any time and decoded by passes that cover every
+ * active frame of every code; frames at different rounds share a pass, so
+ * newly admitted frames join the ones in flight.  A frame stops exactly as in
+ * ldpc_fd_decode (same kernels and per-frame arithmetic, so its results do not
+ * depend on what else is in the pool); stopped frames are harvested and their
+ * slots freed.  All pool calls are ordered on the pool's stream; the pool is
+ * not thread-safe.  The codes must outlive the pool. */
+typedef struct ldpc_fd_pool_s *ldpc_fd_pool;
+
+/* Device bytes one frame slot of `code` occupies at storage precision prec. */
+int32_t ldpc_fd_pool_slot_bytes(ldpc_fd_code code, int32_t prec, int64_t *bytes);
+
+/* Create a pool over codes[0..ncodes) (1..16) with slots[k] frame slots for
+ * code k, message storage prec, operating on `stream` (hipStream_t as void*).
+ * Errors: E_INVALID, E_NOMEM (device or pinned-host allocation), E_HIP. */
+int32_t ldpc_fd_pool_create(const ldpc_fd_code *codes, int32_t ncodes, const int32_t *slots, int32_t prec,
+                            void *stream, ldpc_fd_pool *out);
+
+/* Synchronise the pool's stream and free all its resources (NULL: no-op). */
+int32_t ldpc_fd_pool_destroy(ldpc_fd_pool pool);
+
+/* Number of free slots of code `code` (host-side bookkeeping, no device call). */
+int32_t ldpc_fd_pool_free_slots(ldpc_fd_pool pool, int32_t code, int32_t *n);
+
+/* Admit up to n frames of code `code`: llr is device memory [n][N][m] FP32 that
+ * must stay valid until the pool's stream has passed this call; tags (host,
+ * may be NULL) are returned by harvest.  Frames beyond the free slots are not
+ * admitted; *admitted receives the number taken (from the front of llr).
+ * max_iter >= 1 is the frames' round limit.  Errors: E_INVALID, E_HIP. */
+int32_t ldpc_fd_pool_submit(ldpc_fd_pool pool, int32_t code, const float *llr, int32_t n,
+                            const uint64_t *tags, int32_t max_iter, int32_t *admitted);
+
+/* Enqueue `passes` (1..1000) passes over the active frames of every code: one
+ * replay of a captured graph whose per-code branches run concurrently.
+ * Asynchronous.  Errors: E_INVALID, E_UNSUPPORTED, E_HIP. */
+int32_t ldpc_fd_pool_step(ldpc_fd_pool pool, int32_t passes);
+
+/* Collect up to cap stopped frames of code `code` (synchronises the pool's
+ * stream): tags[cap], iters[cap], status[cap] (LDPC_FD_STATUS_* bits) and
+ * hard[cap][N] (host arrays; any may be NULL).  Their slots become free.
+ * *n receives the number returned.  Errors: E_INVALID, E_HIP. */
+int32_t ldpc_fd_pool_harvest(ldpc_fd_pool pool, int32_t code, int32_t cap, uint64_t *tags, int32_t *iters,
+                             uint32_t *status, uint8_t *hard, int32_t *n);
+
+/* Number of frames of code `code` still being decoded (synchronises). */
+int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
+
 /* Tuning of a code object's kernels (results are identical for every setting;
  * only speed changes).  Set by the autotuner, read back for its cache.
  *   LDPC_FD_TUNE_LANE_ENTRIES: entries of a frame's 2^m-vector held per lane

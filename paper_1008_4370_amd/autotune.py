@@ -1,0 +1,129 @@
+"""Autotuner for the fused decoder's launch choices.
+
+For one code and storage precision it times complete decodes of a synthetic
+batch (random codewords of the code over BPSK/AWGN) for every combination of
+  - entries per lane (4, 8, 16: the kernel variant; each lane holds R entries
+    of a frame's q-point vectors, a wave holds 64 / (q / R) frames),
+  - grid blocks of the fused pass (workgroups of 256 threads, a multiple of 8
+    so that every XCD gets the same share),
+  - rounds per host check (graph chunk),
+keeps the fastest, and stores it in a JSON table keyed by
+(m, kmax, N, E, precision, frames bucket).  `apply(code, prec, frames)` sets a
+code's tuning from the table (library defaults when the key is absent).
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+
+from . import decoder as D
+from . import synth
+
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
+def frames_bucket(F: int) -> int:
+    """Power-of-two bucket of a batch size (tuning depends on it only coarsely)."""
+    return 1 << max(0, int(F - 1).bit_length())
+
+
+def key(code: D.Code, prec: str, frames: int) -> str:
+    m, kmax, N, E = code.m, code.kmax, code.N, code.E
+    return f"m{m}_k{kmax}_N{N}_E{E}_{prec}_F{frames_bucket(frames)}"
+
+
+def lane_choices(m: int, kmax: int):
+    q = 1 << m
+    out = [4]
+    if kmax <= 8 and q >= 8:
+        out.append(8)
+    if kmax <= 8 and 16 <= q <= 128:
+        out.append(16)
+    return out
+
+
+def load_table(path: str = TABLE) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def apply(code: D.Code, prec: str, frames: int, path: str = TABLE) -> dict | None:
+    """Set the tuned launch choices on `code`; returns them (None if untuned)."""
+    ent = load_table(path).get(key(code, prec, frames))
+    if ent is None:
+        return None
+    code.set_tuning(lane_entries=ent["lane_entries"], grid_blocks=ent["grid_blocks"], chunk=ent["chunk"],
+                    graphs=1)
+    return ent
+
+
+def _time_decode(dec, llr, max_iter, reps):
+    import torch
+    dec(llr, max_iter)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        dec(llr, max_iter)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def tune(code: D.Code, llr, prec: str = "fp32", max_iter: int = 100, reps: int = 3,
+         grid_blocks=(2048, 4096, 8192, 16384, 32768), chunks=(4, 8), path: str | None = TABLE, log=None) -> dict:
+    """Sweep the launch choices for decoding `llr` (device [F][N][m]) and record the best."""
+    m, kmax, N = code.m, code.kmax, code.N
+    F = int(llr.shape[0])
+    dec = D.Decoder(code, F, prec, "fused")
+    default = code.get_tuning()
+    default_ms = _time_decode(dec, llr, max_iter, reps) * 1e3
+    results = []
+    for le, gb, ch in itertools.product(lane_choices(m, kmax), grid_blocks, chunks):
+        code.set_tuning(lane_entries=le, grid_blocks=gb, chunk=ch, graphs=1)
+        t = _time_decode(dec, llr, max_iter, reps)
+        results.append((t, le, gb, ch))
+        if log:
+            log(f"[autotune] m={m} k={kmax} N={N} {prec} F={F}: lanes {le} blocks {gb} chunk {ch}: {t * 1e3:.3f} ms")
+    t, le, gb, ch = min(results)
+    ent = {"lane_entries": le, "grid_blocks": gb, "chunk": ch, "ms": round(t * 1e3, 4),
+           "default_ms": round(default_ms, 4),
+           "default": {k: default[k] for k in ("lane_entries", "grid_blocks", "chunk")}, "swept": len(results)}
+    code.set_tuning(lane_entries=le, grid_blocks=gb, chunk=ch, graphs=1)
+    if path:
+        table = load_table(path)
+        table[key(code, prec, F)] = ent
+        with open(path, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+    return ent
+
+
+def tune_workload(name: str, prec: str = "fp32", frames: int | None = None, point: int | None = None,
+                  max_iter: int = 100, path: str | None = TABLE, log=print) -> dict:
+    """Tune on a named synthetic workload (synth.WORKLOADS)."""
+    import torch
+    if point is None:
+        pts = synth.WORKLOADS[name]["ebn0"]
+        point = pts.index(2.5) if 2.5 in pts else 0
+    b = synth.make_batch(name, frames=frames, point=point)
+    code = D.Code.from_synth(b.code)
+    ent = tune(code, torch.from_numpy(b.llr).cuda(), prec, max_iter, path=path, log=log)
+    code.close()
+    return ent
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="tune the fused decoder's launch choices on synthetic workloads")
+    ap.add_argument("workloads", nargs="+")
+    ap.add_argument("--prec", default="fp32")
+    ap.add_argument("--frames", type=int, default=None)
+    ap.add_argument("--point", type=int, default=None)
+    ap.add_argument("--table", default=TABLE)
+    a = ap.parse_args()
+    for w in a.workloads:
+        print(json.dumps({w: tune_workload(w, a.prec, a.frames, a.point, path=a.table)}), flush=True)

@@ -40,6 +40,16 @@ _SIGS = {
     "ldpc_fd_profile_enable": (_i32, [_i32]),
     "ldpc_fd_profile_read": (_i32, [_i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]),
     "ldpc_fd_last_error": (ctypes.c_char_p, []),
+    "ldpc_fd_pool_slot_bytes": (_i32, [_c_void_p, _i32, ctypes.POINTER(_i64)]),
+    "ldpc_fd_pool_create": (_i32, [ctypes.POINTER(_c_void_p), _i32, ctypes.POINTER(_i32), _i32, _c_void_p,
+                                   ctypes.POINTER(_c_void_p)]),
+    "ldpc_fd_pool_destroy": (_i32, [_c_void_p]),
+    "ldpc_fd_pool_free_slots": (_i32, [_c_void_p, _i32, ctypes.POINTER(_i32)]),
+    "ldpc_fd_pool_submit": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _c_void_p, _i32, ctypes.POINTER(_i32)]),
+    "ldpc_fd_pool_step": (_i32, [_c_void_p, _i32]),
+    "ldpc_fd_pool_harvest": (_i32, [_c_void_p, _i32, _i32, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                    ctypes.POINTER(_i32)]),
+    "ldpc_fd_pool_active": (_i32, [_c_void_p, _i32, ctypes.POINTER(_i32)]),
 }
 
 
@@ -191,3 +201,69 @@ def profile_read(kernel: int):
     ms, n = ctypes.c_double(), _i64()
     _check(lib().ldpc_fd_profile_read(int(kernel), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def pool_slot_bytes(code: Code, prec: str = "fp32") -> int:
+    out = _i64()
+    _check(lib().ldpc_fd_pool_slot_bytes(code.handle, PREC[prec], ctypes.byref(out)))
+    return out.value
+
+
+class Pool:
+    """Continuous-batching decode pool over several codes (ldpc_fd_pool_*)."""
+
+    def __init__(self, codes, slots, prec: str = "fp32"):
+        self.codes = list(codes)
+        self.slots = [int(s) for s in slots]
+        arr = (ctypes.c_void_p * len(self.codes))(*[c.handle for c in self.codes])
+        sl = (_i32 * len(self.slots))(*self.slots)
+        h = ctypes.c_void_p()
+        _check(lib().ldpc_fd_pool_create(arr, len(self.codes), sl, PREC[prec], _stream(), ctypes.byref(h)))
+        self.handle = h
+        self.prec = prec
+        self._bufs = [None] * len(self.codes)
+
+    def free_slots(self, k: int) -> int:
+        n = _i32()
+        _check(lib().ldpc_fd_pool_free_slots(self.handle, k, ctypes.byref(n)))
+        return n.value
+
+    def submit(self, k: int, llr, tags, max_iter: int) -> int:
+        """Admit frames llr [n, N, m] (device float32) of code k; returns the number taken."""
+        n = int(llr.shape[0])
+        t = np.ascontiguousarray(np.asarray(tags, dtype=np.uint64)) if tags is not None else None
+        got = _i32()
+        _check(lib().ldpc_fd_pool_submit(self.handle, k, _ptr(llr), n,
+                                         None if t is None else t.ctypes.data, int(max_iter), ctypes.byref(got)))
+        return got.value
+
+    def step(self, passes: int = 1):
+        _check(lib().ldpc_fd_pool_step(self.handle, int(passes)))
+
+    def harvest(self, k: int, cap: int):
+        N = self.codes[k].N
+        if self._bufs[k] is None or self._bufs[k][0].shape[0] < cap:
+            self._bufs[k] = (np.zeros(cap, np.uint64), np.zeros(cap, np.int32), np.zeros(cap, np.uint32),
+                             np.zeros((cap, N), np.uint8))
+        tg, it, st, hd = self._bufs[k]
+        n = _i32()
+        _check(lib().ldpc_fd_pool_harvest(self.handle, k, cap, tg.ctypes.data, it.ctypes.data, st.ctypes.data,
+                                          hd.ctypes.data, ctypes.byref(n)))
+        m = n.value
+        return tg[:m].copy(), it[:m].copy(), st[:m].copy(), hd[:m].copy()
+
+    def active(self, k: int) -> int:
+        n = _i32()
+        _check(lib().ldpc_fd_pool_active(self.handle, k, ctypes.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ldpc_fd_pool_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
