@@ -142,6 +142,31 @@ int32_t ldpc_fd_round(ldpc_fd_code code, int32_t frames, const float *llr, const
                       float *v2c_out, float *c2v_out, uint8_t *hard, uint8_t *fsynd,
                       uint8_t *synd, int32_t mode, int32_t prec, void *stream);
 
+/* ---- Validation mode: FP64 symbol posteriors ----------------------------------
+ * The a-posteriori pmf of every symbol, p_v(x) proportional to the channel pmf
+ * times the pmfs of the two check-to-variable messages of v (Sec. 2.1,
+ * tentative decision; Sec. 3.2 evaluates the same product as a 3-fold
+ * log-convolution).  Each stored message word is widened to P(z) in FP64, taken
+ * back to the probability domain by an FP64 Hadamard transform, multiplied with
+ * the FP64 channel pmf from llr, clamped at zero and normalised in FP64.
+ * posterior: device double[frames][N][2^m], caller-owned, written in full. */
+
+/* From an imported state: c2v = Lambda_cv in the FP32 message layout above
+ * (device [frames][E][2^m], e.g. ldpc_fd_round's c2v_out).
+ * Errors: E_INVALID (NULL code or buffers with frames > 0, frames < 0), E_HIP. */
+int32_t ldpc_fd_posterior(ldpc_fd_code code, int32_t frames, const float *llr, const float *c2v,
+                          double *posterior, void *stream);
+
+/* After an ldpc_fd_decode in FUSED mode with the same code, frames, llr, prec
+ * and workspace (not reused in between): the posterior of each frame at the
+ * round it stopped at (iters[f], the decode's device output), read from the
+ * message buffer that holds that round's check-to-variable messages.
+ * Errors: E_INVALID (NULL arguments with frames > 0, unknown prec, workspace
+ *   smaller than the fused decode's), E_HIP. */
+int32_t ldpc_fd_decode_posterior(ldpc_fd_code code, int32_t frames, const float *llr, int32_t prec,
+                                 const int32_t *iters, const void *workspace, int64_t workspace_bytes,
+                                 double *posterior, void *stream);
+
 /* ---- Decoding pool: continuous batching over several codes -------------------
  * A pool owns, for each of its codes, `slots[k]` frame slots in device memory
  * (message state, decisions and per-frame round counter; ldpc_fd_pool_slot_bytes

@@ -696,3 +696,4 @@ int32_t ldpc_fd_profile_read(int32_t kernel, double* ms, int64_t* launches) {
 }  // extern "C"
 
 #include "pool.inc"
+#include "posterior.inc"

@@ -35,6 +35,9 @@ _SIGS = {
                               _c_void_p, _c_void_p, _i64, _c_void_p]),
     "ldpc_fd_round": (_i32, [_c_void_p, _i32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
                              _c_void_p, _i32, _i32, _c_void_p]),
+    "ldpc_fd_posterior": (_i32, [_c_void_p, _i32, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "ldpc_fd_decode_posterior": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _c_void_p, _c_void_p, _i64, _c_void_p,
+                                        _c_void_p]),
     "ldpc_fd_set_tuning": (_i32, [_c_void_p, _i32, _i32]),
     "ldpc_fd_get_tuning": (_i32, [_c_void_p, _i32, ctypes.POINTER(_i32)]),
     "ldpc_fd_profile_enable": (_i32, [_i32]),
@@ -169,7 +172,20 @@ class Decoder:
         _check(lib().ldpc_fd_decode(self.code.handle, F, _ptr(llr), int(max_iter), PREC[self.prec],
                                     MODE[self.mode], _ptr(self.hard), _ptr(self.synd), _ptr(self.iters),
                                     _ptr(self.status), _ptr(self.workspace), self.ws_bytes, _stream()))
+        self._last = (llr, F)
         return dict(hard=self.hard[:F], synd=self.synd[:F], iters=self.iters[:F], status=self.status[:F])
+
+    def posterior(self):
+        """Validation mode: FP64 posteriors [F, N, q] of the last decode's frames
+        at their stopping rounds (FUSED mode; ldpc_fd_decode_posterior)."""
+        import torch
+        if self.mode != "fused":
+            raise ValueError("posteriors of a decode need the fused mode's message buffers")
+        llr, F = self._last
+        out = torch.empty((F, self.code.N, self.code.q), dtype=torch.float64, device=llr.device)
+        _check(lib().ldpc_fd_decode_posterior(self.code.handle, F, _ptr(llr), PREC[self.prec], _ptr(self.iters),
+                                              _ptr(self.workspace), self.ws_bytes, _ptr(out), _stream()))
+        return out
 
 
 def decode(code: Code, llr, max_iter: int, prec: str = "fp32", mode: str = "fused"):
@@ -190,6 +206,17 @@ def round_step(code: Code, llr, c2v_in=None, mode: str = "plain", prec: str = "f
     _check(lib().ldpc_fd_round(code.handle, F, _ptr(llr), _ptr(c2v_in), _ptr(v2c_out), _ptr(c2v_out),
                                _ptr(hard), _ptr(fsynd), _ptr(synd), MODE[mode], PREC[prec], _stream()))
     return dict(c2v=c2v_out, v2c=v2c_out, hard=hard, fsynd=fsynd, synd=synd)
+
+
+def posterior(code: Code, llr, c2v):
+    """Validation mode: FP64 posteriors [F, N, q] from an FP32 check-to-variable
+    state [F, E, q] (ldpc_fd_posterior)."""
+    import torch
+    F = llr.shape[0]
+    assert c2v.dtype == torch.float32 and c2v.is_contiguous() and tuple(c2v.shape) == (F, code.E, code.q)
+    out = torch.empty((F, code.N, code.q), dtype=torch.float64, device=llr.device)
+    _check(lib().ldpc_fd_posterior(code.handle, F, _ptr(llr), _ptr(c2v), _ptr(out), _stream()))
+    return out
 
 
 def profile_enable(on: bool = True):
