@@ -227,12 +227,16 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *   LDPC_FD_TUNE_CHUNK: rounds between host reads of the active-frame count.
  *   LDPC_FD_TUNE_GRAPHS: 1 (default) = the FUSED decoder captures a chunk of
  *     rounds into a HIP graph once per (frames, buffers, settings) and replays
- *     it; 0 = launch every kernel from the host.  Replayed chunks round the
- *     chunk up to an even number of rounds.  While kernel timing is enabled
- *     (ldpc_fd_profile_enable) kernels are launched from the host.
+ *     it; 0 = launch every kernel from the host.  While kernel timing is
+ *     enabled (ldpc_fd_profile_enable) kernels are launched from the host.
+ *   LDPC_FD_TUNE_TAIL_ENTRIES, LDPC_FD_TUNE_TAIL_FRAMES: a chunk of rounds
+ *     that starts with at most TAIL_FRAMES active frames (default 128) runs
+ *     the variant with TAIL_ENTRIES entries per lane (default 4): with few
+ *     frames left a pass is bound by one check's latency, which more lanes
+ *     per frame shorten.  TAIL_FRAMES = 0 keeps one variant throughout.
  * Errors: E_INVALID (unknown key or value), E_UNSUPPORTED (no such variant). */
 enum { LDPC_FD_TUNE_LANE_ENTRIES = 0, LDPC_FD_TUNE_GRID_BLOCKS = 1, LDPC_FD_TUNE_CHUNK = 2,
-       LDPC_FD_TUNE_GRAPHS = 3 };
+       LDPC_FD_TUNE_GRAPHS = 3, LDPC_FD_TUNE_TAIL_ENTRIES = 4, LDPC_FD_TUNE_TAIL_FRAMES = 5 };
 int32_t ldpc_fd_set_tuning(ldpc_fd_code code, int32_t key, int32_t value);
 int32_t ldpc_fd_get_tuning(ldpc_fd_code code, int32_t key, int32_t *value);
 

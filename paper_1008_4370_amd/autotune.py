@@ -7,6 +7,7 @@ batch (random codewords of the code over BPSK/AWGN) for every combination of
   - grid blocks of the fused pass (workgroups of 256 threads, a multiple of 8
     so that every XCD gets the same share),
   - rounds per host check (graph chunk),
+  - the variant used once few frames are left and its threshold,
 keeps the fastest, and stores it in a JSON table keyed by
 (m, kmax, N, E, precision, frames bucket).  `apply(code, prec, frames)` sets a
 code's tuning from the table (library defaults when the key is absent).
@@ -58,6 +59,8 @@ def apply(code: D.Code, prec: str, frames: int, path: str = TABLE) -> dict | Non
         return None
     code.set_tuning(lane_entries=ent["lane_entries"], grid_blocks=ent["grid_blocks"], chunk=ent["chunk"],
                     graphs=1)
+    if "tail_entries" in ent:
+        code.set_tuning(tail_entries=ent["tail_entries"], tail_frames=ent["tail_frames"])
     return ent
 
 
@@ -75,25 +78,39 @@ def _time_decode(dec, llr, max_iter, reps):
 
 
 def tune(code: D.Code, llr, prec: str = "fp32", max_iter: int = 100, reps: int = 3,
-         grid_blocks=(2048, 4096, 8192, 16384, 32768), chunks=(4, 8), path: str | None = TABLE, log=None) -> dict:
-    """Sweep the launch choices for decoding `llr` (device [F][N][m]) and record the best."""
+         grid_blocks=(2048, 4096, 8192, 16384, 32768), chunks=(4, 8), tail_frames=(0, 32, 128, 512),
+         path: str | None = TABLE, log=None) -> dict:
+    """Sweep the launch choices for decoding `llr` (device [F][N][m]) and record
+    the best: first the main variant, grid and chunk (tail variant at its
+    defaults), then the tail variant and its threshold."""
     m, kmax, N = code.m, code.kmax, code.N
     F = int(llr.shape[0])
     dec = D.Decoder(code, F, prec, "fused")
     default = code.get_tuning()
     default_ms = _time_decode(dec, llr, max_iter, reps) * 1e3
-    results = []
-    for le, gb, ch in itertools.product(lane_choices(m, kmax), grid_blocks, chunks):
-        code.set_tuning(lane_entries=le, grid_blocks=gb, chunk=ch, graphs=1)
+
+    def run(**kw):
+        code.set_tuning(graphs=1, **kw)
         t = _time_decode(dec, llr, max_iter, reps)
-        results.append((t, le, gb, ch))
         if log:
-            log(f"[autotune] m={m} k={kmax} N={N} {prec} F={F}: lanes {le} blocks {gb} chunk {ch}: {t * 1e3:.3f} ms")
-    t, le, gb, ch = min(results)
-    ent = {"lane_entries": le, "grid_blocks": gb, "chunk": ch, "ms": round(t * 1e3, 4),
-           "default_ms": round(default_ms, 4),
-           "default": {k: default[k] for k in ("lane_entries", "grid_blocks", "chunk")}, "swept": len(results)}
-    code.set_tuning(lane_entries=le, grid_blocks=gb, chunk=ch, graphs=1)
+            log(f"[autotune] m={m} k={kmax} N={N} {prec} F={F}: {kw}: {t * 1e3:.3f} ms")
+        return t
+
+    main = []
+    for le, gb, ch in itertools.product(lane_choices(m, kmax), grid_blocks, chunks):
+        main.append((run(lane_entries=le, grid_blocks=gb, chunk=ch, tail_entries=default["tail_entries"],
+                         tail_frames=default["tail_frames"]), le, gb, ch))
+    t_main, le, gb, ch = min(main)
+    tail = [(t_main, default["tail_entries"], default["tail_frames"])]
+    for te, tf in itertools.product(lane_choices(m, kmax), tail_frames):
+        tail.append((run(lane_entries=le, grid_blocks=gb, chunk=ch, tail_entries=te, tail_frames=tf), te, tf))
+    t, te, tf = min(tail)
+    ent = {"lane_entries": le, "grid_blocks": gb, "chunk": ch, "tail_entries": te, "tail_frames": tf,
+           "ms": round(t * 1e3, 4), "default_ms": round(default_ms, 4),
+           "default": {k: default[k] for k in ("lane_entries", "grid_blocks", "chunk", "tail_entries",
+                                               "tail_frames")},
+           "swept": len(main) + len(tail) - 1}
+    code.set_tuning(lane_entries=le, grid_blocks=gb, chunk=ch, tail_entries=te, tail_frames=tf, graphs=1)
     if path:
         table = load_table(path)
         table[key(code, prec, F)] = ent

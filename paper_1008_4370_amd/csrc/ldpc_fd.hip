@@ -38,13 +38,16 @@ struct ldpc_fd_code_s {
   // tuning (ldpc_fd_set_tuning): log2 entries per lane, fused grid cap, rounds per
   // host check, replay of captured round chunks
   int logr = 4, blocks = 2048, chunk = 4, graphs = 1;
+  // chunks that start with at most tail_frames active frames use the variant
+  // with 2^tail_logr entries per lane (shorter per-item latency)
+  int tail_logr = 2, tail_frames = 128;
   int device = 0;
   std::vector<void*> allocs;
   DevCode dev{};
   // Captured chunks of rounds of the fused decoder, keyed by everything their
   // kernel arguments depend on.
   struct GraphKey {
-    int F, prec, chunk, max_iter, logr, blocks, prof;
+    int F, prec, chunk, max_iter, logr, blocks, tail;
     const void *ws, *llr, *hard, *synd, *iters, *status;
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
   };
@@ -186,7 +189,7 @@ struct FusedWs {
   int* tmp;
   uint32_t* unsat;
   uint32_t* mism;
-  int* nact;
+  int* nact;       // nact[0]: active frames; nact[2]: syndrome/retire ticket
   int* rnd;  // [F] per-frame round
 };
 
@@ -217,7 +220,7 @@ size_t fused_layout(const ldpc_fd_code_s* c, int F, int prec, char* base, FusedW
   char* p4 = take((size_t)F * 4);
   char* p5 = take((size_t)F * 4);
   char* p6 = take((size_t)F * 4);
-  char* p7 = take(4);
+  char* p7 = take(16);
   char* p8 = take((size_t)F * 4);
   if (w)
     *w = FusedWs{(float*)pt, {b0, b1}, (uint8_t*)p2, (int*)p3, (int*)p4, (uint32_t*)p5, (uint32_t*)p6, (int*)p7, (int*)p8};
@@ -255,6 +258,26 @@ void launch_syndrome(const ldpc_fd_code_s* c, int F, const uint8_t* hard, const 
   } else {
     hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, c->dev, hard, fsw, synd,
                        fsynd, unsat, mism, alist, nact, F, active, rnd);
+  }
+}
+
+// Syndromes of the active frames, stopping rule and compaction.  tail_grid > 0
+// (at most that many frames are active): one launch of k_syndrome_retire with
+// tail_grid workgroups; otherwise the syndrome kernel and k_retire_compact.
+// ticket = nact + 2 (zero between launches).
+void launch_syndrome_retire(const ldpc_fd_code_s* c, int F, const uint8_t* hard, const uint8_t* fsw, uint8_t* synd,
+                            uint32_t* unsat, uint32_t* mism, int* alist, int* nact, int* rnd, int maxit_all,
+                            const int* maxit, int* tmp, int32_t* iters, uint32_t* status, int* done, int* ndone,
+                            int tail_grid, hipStream_t s) {
+  const size_t lds = 4 * (size_t)(((c->N + 3) >> 2) + ((c->E + 3) >> 2));
+  if (tail_grid > 0 && lds <= 60000) {
+    hipLaunchKernelGGL(k_syndrome_retire, dim3((unsigned)std::min(F, tail_grid)), dim3(256), lds, s, c->dev, hard, fsw,
+                       synd, unsat, mism, alist, nact, rnd, maxit_all, maxit, tmp, iters, status, done, ndone,
+                       (unsigned*)(nact + 2));
+  } else {
+    launch_syndrome(c, F, hard, fsw, synd, nullptr, unsat, mism, alist, nact, nullptr, s, rnd);
+    hipLaunchKernelGGL(k_retire_compact, dim3(1), dim3(1024), 0, s, maxit_all, maxit, alist, tmp, nact, unsat, mism,
+                       iters, status, rnd, done, ndone);
   }
 }
 
@@ -471,10 +494,10 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
   launch_prior(c, F, llr, w.prior, s);
   // One pass over the active frames (each at its own round, see k_fused),
   // syndromes of the decisions it formed, stopping rule and compaction.
-  auto enqueue_round = [&](hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  auto enqueue_round = [&](hipStream_t st, hipEvent_t e0, hipEvent_t e1, int lr, bool tail) {
     bool ok = true;
     if (e0) (void)hipEventRecord(e0, st);
-    ok = dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
+    ok = dispatch(c->m, c->kmax, lr, [&](auto impl) {
       using I = decltype(impl);
       if (prec == LDPC_FD_FP32)
         I::template fused<float>(cd, F, w.prior, (float*)w.buf[0], (float*)w.buf[1], hard, w.fsw, w.alist, w.nact,
@@ -487,16 +510,20 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
                                   w.nact, w.rnd, nullptr, max_iter, c->blocks, st);
     });
     if (e1) (void)hipEventRecord(e1, st);
-    launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, w.alist, w.nact, nullptr, st, w.rnd);
-    hipLaunchKernelGGL(k_retire_compact, dim3(1), dim3(1024), 0, st, max_iter, (const int*)nullptr, w.alist, w.tmp,
-                       w.nact, w.unsat, w.mism, iters, status, w.rnd, (int*)nullptr, (int*)nullptr);
+    launch_syndrome_retire(c, F, hard, w.fsw, synd, w.unsat, w.mism, w.alist, w.nact, w.rnd, max_iter, nullptr, w.tmp,
+                           iters, status, nullptr, nullptr, tail ? std::max(c->tail_frames, 1) : 0, st);
     return ok;
   };
   // A frame needs at most max_iter + 1 passes (pass l forms round l's decision).
   const int passes = max_iter + 1;
   // Kernel timing needs per-launch events, which HIP cannot time inside a
   // replayed graph: profiled decodes launch every pass from the host.
+  // Kernel variant of a chunk of passes, from the active count at its start.
+  auto is_tail = [&](int left) { return left <= c->tail_frames; };
+  auto variant = [&](int left) { return is_tail(left) ? c->tail_logr : c->logr; };
   if (!c->graphs || t_prof.on) {
+    int lr = variant(F);
+    bool tail = is_tail(F);
     for (int p = 1; p <= passes; ++p) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (t_prof.on) {
@@ -504,11 +531,13 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
         e1 = t_prof.get();
         if (e0 && e1) t_prof.ev[LDPC_FD_K_FUSED].emplace_back(e0, e1);
       }
-      if (!enqueue_round(s, e0, e1)) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+      if (!enqueue_round(s, e0, e1, lr, tail)) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
       if (p % c->chunk == 0 || p == passes) {
         int left = 0;
         if ((rc = read_count(w.nact, s, &left))) return rc;
         if (left == 0) break;
+        lr = variant(left);
+        tail = is_tail(left);
       }
     }
     HIP_TRY(hipGetLastError());
@@ -517,20 +546,37 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
   // Replay a captured chunk of passes; passes after every frame has stopped
   // find an empty active list and do nothing.
   const int chunk = c->chunk;
-  ldpc_fd_code_s::GraphKey key{F, prec, chunk, max_iter, c->logr, c->blocks, 0,
-                               workspace, llr, hard, synd, iters, status};
   std::lock_guard<std::mutex> lock(c->gmu);
-  ldpc_fd_code_s::GraphEntry* ge = nullptr;
-  for (auto& g : c->gcache)
-    if (g.key == key) ge = &g;
-  if (!ge) {
+  // The captured chunk for kernel variant lr (found in or added to the cache).
+  auto chunk_graph = [&](int lr, bool tail, hipGraphExec_t* exec) -> int32_t {
+    // zero-filled first: keys compare with memcmp, padding included
+    ldpc_fd_code_s::GraphKey key;
+    std::memset(&key, 0, sizeof key);
+    key.F = F;
+    key.prec = prec;
+    key.chunk = chunk;
+    key.max_iter = max_iter;
+    key.logr = lr;
+    key.blocks = c->blocks;
+    key.tail = tail ? 1 : 0;
+    key.ws = workspace;
+    key.llr = llr;
+    key.hard = hard;
+    key.synd = synd;
+    key.iters = iters;
+    key.status = status;
+    for (auto& g : c->gcache)
+      if (g.key == key) {
+        *exec = g.exec;
+        return LDPC_FD_OK;
+      }
     if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     if (c->gcache.size() >= 8) c->drop_graphs();
     ldpc_fd_code_s::GraphEntry g{key, nullptr, {}};
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     bool ok = true;
-    for (int r = 0; r < chunk; ++r) ok = enqueue_round(c->cap_stream, nullptr, nullptr) && ok;
+    for (int r = 0; r < chunk; ++r) ok = enqueue_round(c->cap_stream, nullptr, nullptr, lr, tail) && ok;
     HIP_TRY(hipStreamEndCapture(c->cap_stream, &graph));
     if (!ok) {
       (void)hipGraphDestroy(graph);
@@ -540,11 +586,14 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
     (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) return fail(LDPC_FD_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
     c->gcache.push_back(g);
-    ge = &c->gcache.back();
-  }
+    *exec = g.exec;
+    return LDPC_FD_OK;
+  };
+  int left = F;
   for (int p = 0; p < passes; p += chunk) {
-    HIP_TRY(hipGraphLaunch(ge->exec, s));
-    int left = 0;
+    hipGraphExec_t exec = nullptr;
+    if ((rc = chunk_graph(variant(left), is_tail(left), &exec))) return rc;
+    HIP_TRY(hipGraphLaunch(exec, s));
     if ((rc = read_count(w.nact, s, &left))) return rc;
     if (left == 0) break;
   }
@@ -653,6 +702,16 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
       if (value != 0 && value != 1) return fail(LDPC_FD_E_INVALID, "graphs: 0 or 1");
       c->graphs = value;
       return LDPC_FD_OK;
+    case LDPC_FD_TUNE_TAIL_ENTRIES:
+      if (value != 4 && value != 8 && value != 16) return fail(LDPC_FD_E_INVALID, "entries per lane: 4, 8 or 16");
+      if (value > c->q || (value == 16 && c->m == 8) || (value > 4 && c->kmax > 8))
+        return fail(LDPC_FD_E_UNSUPPORTED, "no kernel variant with that many entries per lane for this code");
+      c->tail_logr = value == 4 ? 2 : value == 8 ? 3 : 4;
+      return LDPC_FD_OK;
+    case LDPC_FD_TUNE_TAIL_FRAMES:
+      if (value < 0) return fail(LDPC_FD_E_INVALID, "tail frames < 0");
+      c->tail_frames = value;
+      return LDPC_FD_OK;
     default:
       return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
@@ -665,6 +724,8 @@ int32_t ldpc_fd_get_tuning(ldpc_fd_code c, int32_t key, int32_t* value) {
     case LDPC_FD_TUNE_GRID_BLOCKS: *value = c->blocks; return LDPC_FD_OK;
     case LDPC_FD_TUNE_CHUNK: *value = c->chunk; return LDPC_FD_OK;
     case LDPC_FD_TUNE_GRAPHS: *value = c->graphs; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_TAIL_ENTRIES: *value = 1 << c->tail_logr; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_TAIL_FRAMES: *value = c->tail_frames; return LDPC_FD_OK;
     default: return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
 }

@@ -432,23 +432,18 @@ __global__ void k_prior_factors(const float* __restrict__ llr, float* __restrict
 // s_c = sum_{v in V_c} h_cv x^_v and the Fourier word = XOR of the check's
 // edge words (edges of a check are contiguous).  unsat[f] / mism[f] are set to
 // whether any check is nonzero / any pair differs.
-__global__ __launch_bounds__(256) void k_syndrome_frames(DevCode cd, const uint8_t* __restrict__ hard,
-                                                         const uint8_t* __restrict__ fsw,
-                                                         uint8_t* __restrict__ synd, uint8_t* __restrict__ fsynd,
-                                                         uint32_t* __restrict__ unsat, uint32_t* __restrict__ mism,
-                                                         const int* __restrict__ alist,
-                                                         const int* __restrict__ nact_p, int F_all,
-                                                         const uint32_t* __restrict__ active,
-                                                         const int* __restrict__ rnd) {
-  extern __shared__ uint32_t smw[];
+__device__ __forceinline__ void syndrome_frames_body(const DevCode& cd, const uint8_t* __restrict__ hard,
+                                                     const uint8_t* __restrict__ fsw, uint8_t* __restrict__ synd,
+                                                     uint8_t* __restrict__ fsynd, uint32_t* __restrict__ unsat,
+                                                     uint32_t* __restrict__ mism, const int* __restrict__ alist,
+                                                     int nact, const uint32_t* __restrict__ active,
+                                                     const int* __restrict__ rnd, uint32_t* smw, uint8_t* s_exp,
+                                                     uint16_t* s_log) {
   uint8_t* sh = reinterpret_cast<uint8_t*>(smw);   // [N] (rounded up to words)
   const int nw = (cd.N + 3) >> 2, ew = (cd.E + 3) >> 2;
   uint8_t* sw = reinterpret_cast<uint8_t*>(smw + nw);  // [E]
-  __shared__ uint8_t s_exp[512];
-  __shared__ uint16_t s_log[256];
   for (int i = threadIdx.x; i < 512; i += blockDim.x) s_exp[i] = cd.gexp[i];
   for (int i = threadIdx.x; i < 256; i += blockDim.x) s_log[i] = cd.glog[i];
-  const int nact = nact_p ? *nact_p : F_all;
   const bool wN = (cd.N & 3) == 0, wE = (cd.E & 3) == 0;
   for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
     const int f = alist ? alist[slot] : slot;
@@ -491,6 +486,21 @@ __global__ __launch_bounds__(256) void k_syndrome_frames(DevCode cd, const uint8
   }
 }
 
+__global__ __launch_bounds__(256) void k_syndrome_frames(DevCode cd, const uint8_t* __restrict__ hard,
+                                                         const uint8_t* __restrict__ fsw,
+                                                         uint8_t* __restrict__ synd, uint8_t* __restrict__ fsynd,
+                                                         uint32_t* __restrict__ unsat, uint32_t* __restrict__ mism,
+                                                         const int* __restrict__ alist,
+                                                         const int* __restrict__ nact_p, int F_all,
+                                                         const uint32_t* __restrict__ active,
+                                                         const int* __restrict__ rnd) {
+  extern __shared__ uint32_t smw[];
+  __shared__ uint8_t s_exp[512];
+  __shared__ uint16_t s_log[256];
+  syndrome_frames_body(cd, hard, fsw, synd, fsynd, unsat, mism, alist, nact_p ? *nact_p : F_all, active, rnd, smw,
+                       s_exp, s_log);
+}
+
 // Elementwise conversion between message storage types (n4 groups of 4).
 template <typename Sin, typename Sout>
 __global__ void k_convert(const Sin* __restrict__ in, Sout* __restrict__ out, size_t n4) {
@@ -501,10 +511,15 @@ __global__ void k_convert(const Sin* __restrict__ in, Sout* __restrict__ out, si
   }
 }
 
+// Initial per-frame state; nact[2] (the syndrome/retire ticket of the fused
+// decoder's workspace) is cleared with the active count.
 __global__ void k_init_frames(int F, uint32_t* active, uint32_t* unsat, uint32_t* mism, int* alist,
                               int* nact, int32_t* iters, uint32_t* status, int* rnd, int rnd0) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f == 0 && nact) *nact = F;
+  if (f == 0 && nact) {
+    nact[0] = F;
+    nact[2] = 0;
+  }
   if (f >= F) return;
   if (rnd) rnd[f] = rnd0;
   if (active) active[f] = 1u;
@@ -535,23 +550,23 @@ __global__ void k_retire_plain(int F, int ell, int max_iter, uint32_t* active, u
   mism[f] = 0u;
 }
 
-// FUSED decoder: stopping rule and stable compaction of the active list (single
-// workgroup of 1024 threads).  For each active frame with l = rnd[f] >= 1 the
+// FUSED decoder: stopping rule and stable compaction of the active list by one
+// workgroup of NT threads.  For each active frame with l = rnd[f] >= 1 the
 // decision of round l was formed in the pass: iters = l; the frame stops when
 // both syndromes were zero, or fails at l = max_iter.  Continuing frames
 // advance rnd.  Stopped frames are appended to `done` (when given) for
 // harvesting.
-__global__ __launch_bounds__(1024) void k_retire_compact(int maxit_all, const int* __restrict__ maxit, int* alist,
-                                                         int* tmp, int* nact_p, uint32_t* unsat, uint32_t* mism,
-                                                         int32_t* iters, uint32_t* status, int* rnd, int* done,
-                                                         int* ndone) {
-  __shared__ int wsum[16];
-  __shared__ int base_s;
+template <int NT>
+__device__ __forceinline__ void retire_compact_body(int maxit_all, const int* __restrict__ maxit, int* alist,
+                                                    int* tmp, int* nact_p, uint32_t* unsat, uint32_t* mism,
+                                                    int32_t* iters, uint32_t* status, int* rnd, int* done,
+                                                    int* ndone, int* wsum, int* base_s) {
+  constexpr int NW = NT / 64;
   const int nact = *nact_p;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid == 0) base_s = 0;
+  if (tid == 0) *base_s = 0;
   __syncthreads();
-  for (int start = 0; start < nact; start += 1024) {
+  for (int start = 0; start < nact; start += NT) {
     const int i = start + tid;
     int keep = 0, f = -1, stop = 0;
     if (i < nact) {
@@ -577,21 +592,66 @@ __global__ __launch_bounds__(1024) void k_retire_compact(int maxit_all, const in
     const int pre = __builtin_popcountll(b & ((1ull << lane) - 1ull));
     if (lane == 0) wsum[w] = __builtin_popcountll(b);
     __syncthreads();
-    int off = base_s;
+    int off = *base_s;
     for (int k = 0; k < w; ++k) off += wsum[k];
     if (keep) tmp[off + pre] = f;
     __syncthreads();
     if (tid == 0) {
       int s2 = 0;
-      for (int k = 0; k < 16; ++k) s2 += wsum[k];
-      base_s += s2;
+      for (int k = 0; k < NW; ++k) s2 += wsum[k];
+      *base_s += s2;
     }
     __syncthreads();
   }
-  const int total = base_s;
-  for (int i = tid; i < total; i += 1024) alist[i] = tmp[i];
+  const int total = *base_s;
+  for (int i = tid; i < total; i += NT) alist[i] = tmp[i];
   __syncthreads();
   if (tid == 0) *nact_p = total;
+}
+
+// The same as a kernel of one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_retire_compact(int maxit_all, const int* __restrict__ maxit, int* alist,
+                                                         int* tmp, int* nact_p, uint32_t* unsat, uint32_t* mism,
+                                                         int32_t* iters, uint32_t* status, int* rnd, int* done,
+                                                         int* ndone) {
+  __shared__ int wsum[16];
+  __shared__ int base_s;
+  retire_compact_body<1024>(maxit_all, maxit, alist, tmp, nact_p, unsat, mism, iters, status, rnd, done, ndone,
+                            wsum, &base_s);
+}
+
+// Syndromes of the active frames and, in the workgroup that finishes last, the
+// stopping rule and compaction (k_retire_compact's work), in one launch: every
+// workgroup that checked a frame publishes its flags (device-scope release),
+// every workgroup takes a ticket, and the holder of the last ticket acquires
+// the flags and retires.  No workgroup waits for another.  A release writes
+// back the XCD's L2, so this form is for passes with few active frames (a few
+// releases); *ticket is zero on entry and reset by the last workgroup.
+__global__ __launch_bounds__(256) void k_syndrome_retire(DevCode cd, const uint8_t* __restrict__ hard,
+                                                         const uint8_t* __restrict__ fsw, uint8_t* __restrict__ synd,
+                                                         uint32_t* unsat, uint32_t* mism, int* alist, int* nact_p,
+                                                         int* rnd, int maxit_all, const int* __restrict__ maxit,
+                                                         int* tmp, int32_t* iters, uint32_t* status, int* done,
+                                                         int* ndone, unsigned* ticket) {
+  extern __shared__ uint32_t smw[];
+  __shared__ uint8_t s_exp[512];
+  __shared__ uint16_t s_log[256];
+  __shared__ int wsum[4];
+  __shared__ int base_s;
+  __shared__ int last;
+  const int nact = *nact_p;
+  syndrome_frames_body(cd, hard, fsw, synd, nullptr, unsat, mism, alist, nact, nullptr, rnd, smw, s_exp, s_log);
+  // thread 0 wrote this workgroup's flags (after the body's last barrier)
+  if (threadIdx.x == 0) {
+    if ((int)blockIdx.x < nact) __threadfence();
+    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  retire_compact_body<256>(maxit_all, maxit, alist, tmp, nact_p, unsat, mism, iters, status, rnd, done, ndone, wsum,
+                           &base_s);
+  if (threadIdx.x == 0) *ticket = 0u;
 }
 
 }  // namespace ldpcfd

@@ -35,4 +35,7 @@ def test_committed_table_is_valid():
         assert ent["lane_entries"] in autotune.lane_choices(m, kmax), k
         assert ent["grid_blocks"] % 8 == 0 and 8 <= ent["grid_blocks"] <= 1 << 20, k
         assert 1 <= ent["chunk"] <= 64, k
+        if "tail_entries" in ent:
+            assert ent["tail_entries"] in autotune.lane_choices(m, kmax), k
+            assert ent["tail_frames"] >= 0, k
         assert ent["ms"] <= ent["default_ms"] * 1.05, k
