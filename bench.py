@@ -187,6 +187,10 @@ def main():
     ap.add_argument("--serve-load", type=float, default=100000.0,
                     help="offered frames/s of the serving phase that measures p50/p99 frame latency (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--precise", action="store_true",
+                    help="time the FP64 variable node (tuning key PRECISE) as the headline")
+    ap.add_argument("--no-precise-variant", action="store_true",
+                    help="skip the extra timing of the FP64 variable node")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (calibrates rocprofv3 "
                          "FETCH_SIZE/WRITE_SIZE against a known byte count) and exit")
@@ -232,6 +236,8 @@ def main():
         tune["graphs"] = args.graphs
     if tune:
         code.set_tuning(**tune)
+    if args.precise:
+        code.set_tuning(precise=1)
     dec = D.Decoder(code, F, args.prec, args.mode)
     llr = torch.from_numpy(batch.llr).cuda()
     for _ in range(args.warmup):
@@ -250,6 +256,31 @@ def main():
     kms, launches = D.profile_read(kernel)
     ms_var, launches_var = D.profile_read(D.K_VAR)
     ms_step = (t1 - t0) / args.steps * 1e3
+
+    precise_line = None
+    if args.mode == "fused" and not args.precise and not args.no_precise_variant:
+        # The same batch with the FP64 variable node (tuning key PRECISE), for
+        # the throughput / frame-error trade-off; not the headline value.
+        before = code.get_tuning()
+        # FP64 registers: 8 entries per lane where the code has that variant
+        if code.kmax <= 8 and code.m >= 3:
+            code.set_tuning(lane_entries=8)
+        code.set_tuning(precise=1)
+        pdec = D.Decoder(code, F, args.prec, args.mode)
+        pdec(llr, args.max_iter)
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for _ in range(args.steps):
+            pout = pdec(llr, args.max_iter)
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - tp0) / args.steps * 1e3
+        phard = pout["hard"].cpu().numpy()
+        precise_line = {"ms_per_step": round(pms, 4),
+                        "value": round(F * batch.info_bits_per_frame / (pms / 1e3) / 1e6, 3),
+                        "fer": float(np.any(phard != batch.cw, axis=1).mean()),
+                        "tuning": code.get_tuning()}
+        code.set_tuning(**before)
+        del pdec
 
     serve = None
     if args.serve_load > 0:
@@ -322,6 +353,7 @@ def main():
             "kernel_ms_per_step": round(kms / args.steps, 4),
         },
         "cpu_baseline": cpu,
+        "precise_variant": precise_line,
         "fer": float(frame_err.mean()),
         "ber": bit_err / (F * batch.code.N * batch.code.m),
         "mean_iters": float(iters.mean()),

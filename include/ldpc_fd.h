@@ -218,8 +218,8 @@ int32_t ldpc_fd_pool_harvest(ldpc_fd_pool pool, int32_t code, int32_t cap, uint6
 /* Number of frames of code `code` still being decoded (synchronises). */
 int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
 
-/* Tuning of a code object's kernels (results are identical for every setting;
- * only speed changes).  Set by the autotuner, read back for its cache.
+/* Tuning of a code object's kernels (results are identical for every setting
+ * except LDPC_FD_TUNE_PRECISE; only speed changes).  Set by the autotuner, read back for its cache.
  *   LDPC_FD_TUNE_LANE_ENTRIES: entries of a frame's 2^m-vector held per lane
  *     (4, 8 or 16; 16 needs m <= 7, rows of weight > 8 use 4).  Fewer entries
  *     per lane means more lanes per frame, fewer registers and more waves.
@@ -234,9 +234,17 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *     the variant with TAIL_ENTRIES entries per lane (default 4): with few
  *     frames left a pass is bound by one check's latency, which more lanes
  *     per frame shorten.  TAIL_FRAMES = 0 keeps one variant throughout.
+ *   LDPC_FD_TUNE_PRECISE: 1 = the FUSED pass evaluates the variable node (prior
+ *     convolution and normalisation, Sec. 3.2 VARIABLE TO CHECK) in FP64 from the
+ *     stored words, with 1 - |P| and 1 - |tanh(L/2)| carried at FP32 relative
+ *     precision; 0 (default) = FP32.  Unlike the other keys this one changes
+ *     results: FP32 loses the small differences from certainty that decide
+ *     messages where the channel and the check messages disagree.  A pool uses
+ *     the setting its codes had when it was created.
  * Errors: E_INVALID (unknown key or value), E_UNSUPPORTED (no such variant). */
 enum { LDPC_FD_TUNE_LANE_ENTRIES = 0, LDPC_FD_TUNE_GRID_BLOCKS = 1, LDPC_FD_TUNE_CHUNK = 2,
-       LDPC_FD_TUNE_GRAPHS = 3, LDPC_FD_TUNE_TAIL_ENTRIES = 4, LDPC_FD_TUNE_TAIL_FRAMES = 5 };
+       LDPC_FD_TUNE_GRAPHS = 3, LDPC_FD_TUNE_TAIL_ENTRIES = 4, LDPC_FD_TUNE_TAIL_FRAMES = 5,
+       LDPC_FD_TUNE_PRECISE = 6 };
 int32_t ldpc_fd_set_tuning(ldpc_fd_code code, int32_t key, int32_t value);
 int32_t ldpc_fd_get_tuning(ldpc_fd_code code, int32_t key, int32_t *value);
 

@@ -41,6 +41,8 @@ struct ldpc_fd_code_s {
   // chunks that start with at most tail_frames active frames use the variant
   // with 2^tail_logr entries per lane (shorter per-item latency)
   int tail_logr = 2, tail_frames = 128;
+  // 1: the fused pass evaluates the variable node in FP64 (see conv_prior_d)
+  int precise = 0;
   int device = 0;
   std::vector<void*> allocs;
   DevCode dev{};
@@ -124,10 +126,14 @@ struct Impl {
   template <typename S>
   static void fused(const DevCode& cd, int Fmax, const float* prior, S* buf0, S* buf1, uint8_t* hard, uint8_t* fsw,
                     const int* alist, const int* nact, const int* rnd, const int* maxit, int maxit_all, int cap,
-                    hipStream_t s) {
+                    bool precise, hipStream_t s) {
     if (Fmax == 0) return;
-    hipLaunchKernelGGL((k_fused<G, KMAX, S>), dim3(fused_blocks(cd, Fmax, cap)), dim3(64 * kWaves), lds(), s, cd,
-                       prior, buf0, buf1, hard, fsw, alist, nact, rnd, maxit, maxit_all);
+    if (precise)
+      hipLaunchKernelGGL((k_fused<G, KMAX, S, true>), dim3(fused_blocks(cd, Fmax, cap)), dim3(64 * kWaves), lds(), s,
+                         cd, prior, buf0, buf1, hard, fsw, alist, nact, rnd, maxit, maxit_all);
+    else
+      hipLaunchKernelGGL((k_fused<G, KMAX, S, false>), dim3(fused_blocks(cd, Fmax, cap)), dim3(64 * kWaves), lds(), s,
+                         cd, prior, buf0, buf1, hard, fsw, alist, nact, rnd, maxit, maxit_all);
   }
 };
 
@@ -243,7 +249,7 @@ unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 void launch_prior(const ldpc_fd_code_s* c, int F, const float* llr, float* prior, hipStream_t s) {
   const size_t n = (size_t)F * c->N * c->m;
   hipLaunchKernelGGL(k_prior_factors, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, llr,
-                     prior, n);
+                     prior, n, c->precise ? 1 : 0);
 }
 
 // Syndromes of the current decisions for the active frames (alist/nact, or all
@@ -501,13 +507,13 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
       using I = decltype(impl);
       if (prec == LDPC_FD_FP32)
         I::template fused<float>(cd, F, w.prior, (float*)w.buf[0], (float*)w.buf[1], hard, w.fsw, w.alist, w.nact,
-                                 w.rnd, nullptr, max_iter, c->blocks, st);
+                                 w.rnd, nullptr, max_iter, c->blocks, c->precise, st);
       else if (prec == LDPC_FD_FP16)
         I::template fused<_Float16>(cd, F, w.prior, (_Float16*)w.buf[0], (_Float16*)w.buf[1], hard, w.fsw, w.alist,
-                                    w.nact, w.rnd, nullptr, max_iter, c->blocks, st);
+                                    w.nact, w.rnd, nullptr, max_iter, c->blocks, c->precise, st);
       else
         I::template fused<bf16_t>(cd, F, w.prior, (bf16_t*)w.buf[0], (bf16_t*)w.buf[1], hard, w.fsw, w.alist,
-                                  w.nact, w.rnd, nullptr, max_iter, c->blocks, st);
+                                  w.nact, w.rnd, nullptr, max_iter, c->blocks, c->precise, st);
     });
     if (e1) (void)hipEventRecord(e1, st);
     launch_syndrome_retire(c, F, hard, w.fsw, synd, w.unsat, w.mism, w.alist, w.nact, w.rnd, max_iter, nullptr, w.tmp,
@@ -657,9 +663,9 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
           if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, in, n_msg / 4);
         }
         if (c2v_in)
-          I::template fused<S>(cd, F, prior, out, in, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, s);
+          I::template fused<S>(cd, F, prior, out, in, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise, s);
         else
-          I::template fused<S>(cd, F, prior, nullptr, out, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, s);
+          I::template fused<S>(cd, F, prior, nullptr, out, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise, s);
         if (prec != LDPC_FD_FP32)
           hipLaunchKernelGGL((k_convert<S, float>), dim3(g), dim3(256), 0, s, (const S*)out, c2v_out, n_msg / 4);
       };
@@ -712,6 +718,10 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
       if (value < 0) return fail(LDPC_FD_E_INVALID, "tail frames < 0");
       c->tail_frames = value;
       return LDPC_FD_OK;
+    case LDPC_FD_TUNE_PRECISE:
+      if (value != 0 && value != 1) return fail(LDPC_FD_E_INVALID, "precise: 0 or 1");
+      c->precise = value;
+      return LDPC_FD_OK;
     default:
       return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
@@ -726,6 +736,7 @@ int32_t ldpc_fd_get_tuning(ldpc_fd_code c, int32_t key, int32_t* value) {
     case LDPC_FD_TUNE_GRAPHS: *value = c->graphs; return LDPC_FD_OK;
     case LDPC_FD_TUNE_TAIL_ENTRIES: *value = 1 << c->tail_logr; return LDPC_FD_OK;
     case LDPC_FD_TUNE_TAIL_FRAMES: *value = c->tail_frames; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_PRECISE: *value = c->precise; return LDPC_FD_OK;
     default: return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
 }

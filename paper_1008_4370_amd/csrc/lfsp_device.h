@@ -156,6 +156,103 @@ __device__ __forceinline__ void conv_prior(float (&v)[G::R], const float (&t)[G:
   }
 }
 
+// ---- precise variable-node arithmetic ------------------------------------------
+// Near-certain messages have |P(z)| = 1 - delta with delta far below the FP32
+// resolution at 1, and reliable channel bits have |t_i| = 1 - u_i likewise.
+// Where the channel and the message disagree, the prior convolution cancels
+// the leading 1s and leaves a result made of the deltas and u's, which FP32
+// values near 1 no longer hold.  The precise form keeps the stored words and
+// the check node as they are and runs the variable node in FP64: words are
+// widened with 1 - 2^-mu formed from mu directly, the prior factors arrive as
+// signed complements c_i = sign(L_i) u_i, the butterflies run in FP64, and the
+// normalised magnitude -log2(Y(z)/Y(0)) of a ratio near 1 comes from a series
+// in 1 - ratio.
+
+__device__ __forceinline__ double lane_xor_d(double v, int mask) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const float lo = lane_xor(__uint_as_float((uint32_t)u), mask);
+  const float hi = lane_xor(__uint_as_float((uint32_t)(u >> 32)), mask);
+  return __longlong_as_double((long long)(((unsigned long long)__float_as_uint(hi) << 32) | __float_as_uint(lo)));
+}
+
+template <class G>
+__device__ __forceinline__ double bcast_frame0_d(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const float lo = bcast_frame0<G>(__uint_as_float((uint32_t)u));
+  const float hi = bcast_frame0<G>(__uint_as_float((uint32_t)(u >> 32)));
+  return __longlong_as_double((long long)(((unsigned long long)__float_as_uint(hi) << 32) | __float_as_uint(lo)));
+}
+
+// sign(w) 2^-|w| in FP64.  For |w| < 1/4, 1 - 2^-|w| = 1 - e^-x (x = |w| ln 2
+// < 0.174) is summed as its Taylor series to x^7 (remainder below 1e-9
+// relative), so the distance from 1 keeps FP32 relative precision.
+__device__ __forceinline__ double gamma_inv_d(float w) {
+  const float mu = __builtin_fabsf(w);
+  const float x = mu * 0.6931471805599453f;
+  float p = __builtin_fmaf(x, 1.0f / 5040.0f, -1.0f / 720.0f);
+  p = __builtin_fmaf(x, p, 1.0f / 120.0f);
+  p = __builtin_fmaf(x, p, -1.0f / 24.0f);
+  p = __builtin_fmaf(x, p, 1.0f / 6.0f);
+  p = __builtin_fmaf(x, p, -0.5f);
+  p = __builtin_fmaf(x, p, 1.0f);
+  const double a = mu < 0.25f ? 1.0 - (double)(x * p) : (double)__builtin_amdgcn_exp2f(-mu);
+  return (__float_as_uint(w) & 0x80000000u) ? -a : a;
+}
+
+// t = sign(c) (1 - |c|) from a signed complement c.
+__device__ __forceinline__ double prior_t_d(float c) {
+  const double a = 1.0 - (double)__builtin_fabsf(c);
+  return (__float_as_uint(c) & 0x80000000u) ? -a : a;
+}
+
+template <class G>
+__device__ __forceinline__ void conv_prior_d(double (&v)[G::R], const float (&c)[G::LOGQ]) {
+#pragma unroll
+  for (int b = 0; b < G::LOGQ; ++b) {
+    const double tb = prior_t_d(c[b]);
+    if (G::lane_bit(b)) {
+      const int mask = 1 << G::lane_shift(b);
+#pragma unroll
+      for (int r = 0; r < G::R; ++r) v[r] = __builtin_fma(tb, lane_xor_d(v[r], mask), v[r]);
+    } else {
+      const int rb = 1 << G::reg_bit(b);
+#pragma unroll
+      for (int r = 0; r < G::R; ++r) {
+        if (!(r & rb)) {
+          const double a = v[r], d = v[r | rb];
+          v[r] = __builtin_fma(tb, d, a);
+          v[r | rb] = __builtin_fma(tb, a, d);
+        }
+      }
+    }
+  }
+}
+
+// Gamma(Y(z) / Y(0)) from FP64 Y: for ratios r >= 15/16, -log2 r =
+// (e + e^2/2 + ... + e^7/7) / ln 2 with e = 1 - r (remainder below 4e-9
+// relative); below, log2 of r rounded to FP32.  Clamped to [0, kLmax].
+template <class G>
+__device__ __forceinline__ void normalise_gamma_d(const double (&y)[G::R], float (&out)[G::R]) {
+  const double y0 = __builtin_fmax(bcast_frame0_d<G>(y[0]), 1e-300);
+  const double inv = 1.0 / y0;
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) {
+    const double rr = __builtin_fabs(y[r]) * inv;
+    const float e = (float)(1.0 - rr);
+    float s = __builtin_fmaf(e, 1.0f / 7.0f, 1.0f / 6.0f);
+    s = __builtin_fmaf(e, s, 1.0f / 5.0f);
+    s = __builtin_fmaf(e, s, 1.0f / 4.0f);
+    s = __builtin_fmaf(e, s, 1.0f / 3.0f);
+    s = __builtin_fmaf(e, s, 0.5f);
+    s = __builtin_fmaf(e, s, 1.0f);
+    const float near1 = e * s * 1.4426950408889634f;
+    const float far = -__builtin_amdgcn_logf((float)rr);
+    const float mag = __builtin_amdgcn_fmed3f(rr >= 0.9375 ? near1 : far, 0.0f, kLmax);
+    out[r] = __uint_as_float((uint32_t)((unsigned long long)__double_as_longlong(y[r]) >> 32 & 0x80000000ull) |
+                             __float_as_uint(mag));
+  }
+}
+
 // ---- unnormalised Walsh-Hadamard transform, up to a lane sign ----------------
 // Returns s(z) V(z) with V(z) = sum_x v(x) (-1)^(z.x) and s(z) = (-1)^popcount(zl)
 // (zl = the lane bits of z): along a lane bit each lane forms own +/- partner,

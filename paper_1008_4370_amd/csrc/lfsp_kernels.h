@@ -9,6 +9,7 @@
 // vectors, done as one butterfly per bit.  The tentative decision reads the
 // signs of the Fourier-domain posterior at alpha^(i-1) and at M_h^T alpha^(i-1).
 #pragma once
+#include <type_traits>
 #include "lfsp_device.h"
 
 namespace ldpcfd {
@@ -267,7 +268,9 @@ __device__ __forceinline__ void issue_edge(const DevCode& cd, const float* __res
   if (any_decide && e < eo && fs.decide) load_msg<G, S>(cin + fb + (size_t)e * G::Q, zl, L.o);
 }
 
-template <class G, int KMAX, typename S>
+// P (precise): the variable node in FP64 (prior factors given as signed
+// complements, see conv_prior_d).
+template <class G, int KMAX, typename S, bool P>
 __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __restrict__ tp, S* __restrict__ buf0,
                                            S* __restrict__ buf1, uint8_t* __restrict__ hard,
                                            uint8_t* __restrict__ fsw, int f, bool valid, const FrameState& fs,
@@ -279,9 +282,12 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
   const bool any_decide = __builtin_amdgcn_ballot_w64(fs.decide && valid) != 0;
   const bool any_write = __builtin_amdgcn_ballot_w64(fs.write && valid) != 0;
   float st[KMAX][G::R];   // Lambda~_vc of each edge (check coordinates)
-  float smag[G::R];
+  // sum of magnitudes over the check's edges (P: FP64, so that a small
+  // extrinsic sum next to a large own term survives total minus own)
+  using Acc = typename std::conditional<P, double, float>::type;
+  Acc smag[G::R];
 #pragma unroll
-  for (int r = 0; r < G::R; ++r) smag[r] = 0.0f;
+  for (int r = 0; r < G::R; ++r) smag[r] = 0;
   // edge j+1's loads are in flight while edge j is computed
   EdgeLoads<G, S> nxt;
   issue_edge<G, S>(cd, tp, cin, fb, f, e0, fs, any_decide, zl, nxt);
@@ -296,11 +302,20 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
       const int h = uni(cd.e_label[e]);
       float t[G::LOGQ];
 #pragma unroll
-      for (int i = 0; i < G::LOGQ; ++i) t[i] = cur.l[i];   // prior factors tanh(L_i / 2)
+      for (int i = 0; i < G::LOGQ; ++i) t[i] = cur.l[i];   // prior factors (P: signed complements)
+      double y64[P ? G::R : 1];
+      if constexpr (P) {
 #pragma unroll
-      for (int r = 0; r < G::R; ++r)
-        st[j][r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
-      conv_prior<G>(st[j], t);
+        for (int r = 0; r < G::R; ++r) y64[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0 : 0.0) : gamma_inv_d(cur.x[r]);
+        conv_prior_d<G>(y64, t);
+#pragma unroll
+        for (int r = 0; r < G::R; ++r) st[j][r] = (float)y64[r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < G::R; ++r)
+          st[j][r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
+        conv_prior<G>(st[j], t);
+      }
       if (any_decide && e < eo) {
         float xo[G::R];
 #pragma unroll
@@ -314,10 +329,13 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
           fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
         }
       }
-      normalise_gamma<G>(st[j]);
+      if constexpr (P)
+        normalise_gamma_d<G>(y64, st[j]);
+      else
+        normalise_gamma<G>(st[j]);
       permute<G>(st[j], lds, rb, cf, zl, uni64(cd.colsT[h]));
 #pragma unroll
-      for (int r = 0; r < G::R; ++r) smag[r] += __builtin_fabsf(st[j][r]);
+      for (int r = 0; r < G::R; ++r) smag[r] += (Acc)__builtin_fabsf(st[j][r]);
     }
   }
   if (!any_write) return;
@@ -339,7 +357,7 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
       float o[G::R];
 #pragma unroll
       for (int r = 0; r < G::R; ++r) {
-        const float mag = __builtin_amdgcn_fmed3f(smag[r] - __builtin_fabsf(st[j][r]), 0.0f, kLmax);
+        const float mag = __builtin_amdgcn_fmed3f((float)(smag[r] - (Acc)__builtin_fabsf(st[j][r])), 0.0f, kLmax);
         o[r] = __uint_as_float(((ssgn[r] ^ __float_as_uint(st[j][r])) & 0x80000000u) | __float_as_uint(mag));
       }
       permute<G>(o, lds, rb, cf, zl, uni64(cd.colsT[hinv]));
@@ -355,7 +373,7 @@ constexpr int kXcds = 8;
 // workgroups of XCD g % 8, so both reads of a message within a pass (as the
 // other edge of its variable, and by its own check at the owner visit) come
 // from the same XCD's L2.  gridDim.x must be a multiple of 8.
-template <class G, int KMAX, typename S>
+template <class G, int KMAX, typename S, bool P>
 __global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restrict__ tp, S* __restrict__ buf0,
                                                S* __restrict__ buf1, uint8_t* __restrict__ hard,
                                                uint8_t* __restrict__ fsw, const int* __restrict__ alist,
@@ -379,7 +397,7 @@ __global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restri
     const bool valid = slot < nact;
     const int f = alist[valid ? slot : nact - 1];
     const FrameState fs = frame_state(rnd, maxit, maxit_all, f);
-    fused_item<G, KMAX, S>(cd, tp, buf0, buf1, hard, fsw, f, valid, fs, c, lds, rb, cf, zl);
+    fused_item<G, KMAX, S, P>(cd, tp, buf0, buf1, hard, fsw, f, valid, fs, c, lds, rb, cf, zl);
   }
 }
 
@@ -417,12 +435,16 @@ __global__ void k_syndrome(DevCode cd, const uint8_t* __restrict__ hard, const u
 // P_v^(0)(z) = prod_{i in z} tanh(L_{v,i}/2).  The passes keep only these m
 // factors per symbol (the same 4 N m bytes as the LLRs) and apply them as the
 // prior convolution; this kernel forms them once per decode.
-__global__ void k_prior_factors(const float* __restrict__ llr, float* __restrict__ t, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const float x = llr[i];
-    const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * __builtin_fabsf(x));  // e^-|L|
-    t[i] = __builtin_copysignf((1.0f - e) / (1.0f + e), x);
-  }
+// comp != 0: the signed complement sign(L) (1 - |tanh(L/2)|) = sign(L) 2 e / (1 + e)
+// instead (precise variable node), exact in FP32 relative precision for reliable bits.
+__device__ __forceinline__ float prior_factor(float x, int comp) {
+  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * __builtin_fabsf(x));  // e^-|L|
+  return __builtin_copysignf((comp ? 2.0f * e : 1.0f - e) / (1.0f + e), x);
+}
+
+__global__ void k_prior_factors(const float* __restrict__ llr, float* __restrict__ t, size_t n, int comp) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    t[i] = prior_factor(llr[i], comp);
 }
 
 // Syndromes of the tentative decision, one workgroup per active frame: the

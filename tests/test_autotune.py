@@ -39,3 +39,14 @@ def test_committed_table_is_valid():
             assert ent["tail_entries"] in autotune.lane_choices(m, kmax), k
             assert ent["tail_frames"] >= 0, k
         assert ent["ms"] <= ent["default_ms"] * 1.05, k
+
+
+def test_fer_helpers():
+    from paper_1008_4370_amd import fer
+    lo, hi = fer.wilson(10, 1000)
+    assert lo < 0.01 < hi and 0.004 < lo and hi < 0.02
+    a = [{"ebn0": 2.0, "fer": 1e-1}, {"ebn0": 2.5, "fer": 1e-3}]
+    b = [{"ebn0": 2.0, "fer": 1e-1}, {"ebn0": 3.0, "fer": 1e-3}]
+    assert abs(fer.crossing_db(a, 1e-2) - 2.25) < 1e-12
+    assert abs(fer.gap_db(a, b, 1e-2) - 0.25) < 1e-12
+    assert fer.crossing_db(a, 1e-4) is None

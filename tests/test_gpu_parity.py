@@ -46,7 +46,7 @@ def _dev(x, dtype=None):
     return t.cuda()
 
 
-@pytest.mark.parametrize("mode", ["plain", "fused"])
+@pytest.mark.parametrize("mode", ["plain", "fused", "fused+precise"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_one_round_message_parity(case, mode):
     """From the same imported state, one GPU round matches the oracle's round:
@@ -56,6 +56,9 @@ def test_one_round_message_parity(case, mode):
     code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0)
     print(f"[case] {name} mode={mode} F={F}", flush=True)
     gcode = D.Code.from_synth(code)
+    if mode == "fused+precise":
+        gcode.set_tuning(precise=1)
+        mode = "fused"
     L = _dev(llr)
     c2vs, v2cs, decs = run_rounds(tc, llr.astype(np.float64), 3)
     # round 0 -> 1 (initial messages)
@@ -259,4 +262,54 @@ def test_graph_replay_matches_eager_launches():
         eager = {k: v.cpu().numpy() for k, v in D.decode(gcode, L, 40, prec="fp32").items()}
         assert all(np.array_equal(eager[k], ref[k]) for k in ref)
         gcode.set_tuning(graphs=1)
+    gcode.close()
+
+
+def test_precise_variable_node_when_channel_and_messages_disagree():
+    """The variable node where reliable channel bits contradict near-certain
+    check messages: the prior convolution cancels the leading 1s, and the result
+    is made of the small differences from certainty.  Messages are
+    near-deterministic pmfs (1 - eps on a random symbol, eps in 1e-6..1e-3
+    spread over the others) and channel bits have |L| in 8..16.  With the FP64
+    variable node (tuning key PRECISE) one GPU round matches the oracle to 1e-4
+    on the well-conditioned entries; the FP32 form's error is printed."""
+    m, k, N, F = 6, 6, 60, 8
+    code, enc, cw, llr, tc = _setup(m, k, N, F, 2.5)
+    q = tc.q
+    print(f"[case] conflict gf64_k6_n60 F={F}", flush=True)
+    rng = np.random.default_rng(123)
+    eps = 10.0 ** rng.uniform(-6, -3, size=(F, tc.E, 1))
+    tail = rng.random((F, tc.E, q))
+    star = rng.integers(0, q, size=(F, tc.E))
+    tail[np.arange(F)[:, None], np.arange(tc.E)[None, :], star] = 0.0
+    pmf = eps * tail / tail.sum(-1, keepdims=True)
+    pmf[np.arange(F)[:, None], np.arange(tc.E)[None, :], star] = 1.0 - eps[..., 0]
+    llr2 = (rng.uniform(8.0, 16.0, size=(F, N, m)) * rng.choice([-1.0, 1.0], size=(F, N, m))).astype(np.float32)
+    p0 = channel_prior(llr2.astype(np.float64), m)
+    words = to_state(pmf)
+    H = hadamard(tc.q)
+
+    def oracle_round(w):
+        return fourier(check_to_var(tc, var_to_check(tc, p0, from_state(w) @ H / tc.q)))
+
+    # The oracle takes the state the GPU gets (the FP32 words).  Entries whose
+    # exact value moves by more than 1e-6 when every word magnitude moves by one
+    # ulp are ill-conditioned for any arithmetic and are left out (~2% here).
+    ref = oracle_round(words)
+    mag = np.abs(words)
+    toward = np.where(rng.random(words.shape) < 0.5, np.inf, 0.0).astype(np.float32)
+    bumped = np.copysign(np.where(mag == 0, mag, np.nextafter(mag, toward)), words).astype(np.float32)
+    well = np.abs(oracle_round(bumped) - ref) < 1e-6
+    gcode = D.Code.from_synth(code)
+    errs = {}
+    for precise in (0, 1):
+        gcode.set_tuning(precise=precise)
+        out = D.round_step(gcode, _dev(llr2), _dev(words), "fused")
+        torch.cuda.synchronize()
+        errs[precise] = float(np.abs(from_state(out["c2v"].cpu().numpy()) - ref)[well].max())
+    print(f"  {well.mean():.1%} of entries well-conditioned; one-round max |dP| on them: "
+          f"FP32 variable node {errs[0]:.2e}, FP64 variable node {errs[1]:.2e}", flush=True)
+    assert well.mean() > 0.9
+    assert errs[1] < TOL_FP32
+    assert errs[1] <= errs[0]
     gcode.close()
