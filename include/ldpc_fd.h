@@ -219,7 +219,7 @@ int32_t ldpc_fd_pool_harvest(ldpc_fd_pool pool, int32_t code, int32_t cap, uint6
 int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
 
 /* Tuning of a code object's kernels (results are identical for every setting
- * except LDPC_FD_TUNE_PRECISE; only speed changes).  Set by the autotuner, read back for its cache.
+ * except LDPC_FD_TUNE_PRECISE and LDPC_FD_TUNE_DECISION_MFMA; only speed changes).  Set by the autotuner, read back for its cache.
  *   LDPC_FD_TUNE_LANE_ENTRIES: entries of a frame's 2^m-vector held per lane
  *     (4, 8 or 16; 16 needs m <= 7, rows of weight > 8 use 4).  Fewer entries
  *     per lane means more lanes per frame, fewer registers and more waves.
@@ -241,10 +241,16 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *     results: FP32 loses the small differences from certainty that decide
  *     messages where the channel and the check messages disagree.  A pool uses
  *     the setting its codes had when it was created.
+ *   LDPC_FD_TUNE_DECISION_MFMA: 1 = the three Hadamard transforms of the
+ *     tentative decision run as FP16 MFMAs with FP32 accumulation (each FP32
+ *     operand split into two FP16 terms, ~22 bits), in the variants with 4
+ *     lanes per frame (2^m = 16, 32, 64; elsewhere, and with PRECISE, the FP32
+ *     VALU transforms are used).  Decisions can differ from the VALU form only
+ *     where a posterior value at a read point is within rounding of zero.
  * Errors: E_INVALID (unknown key or value), E_UNSUPPORTED (no such variant). */
 enum { LDPC_FD_TUNE_LANE_ENTRIES = 0, LDPC_FD_TUNE_GRID_BLOCKS = 1, LDPC_FD_TUNE_CHUNK = 2,
        LDPC_FD_TUNE_GRAPHS = 3, LDPC_FD_TUNE_TAIL_ENTRIES = 4, LDPC_FD_TUNE_TAIL_FRAMES = 5,
-       LDPC_FD_TUNE_PRECISE = 6 };
+       LDPC_FD_TUNE_PRECISE = 6, LDPC_FD_TUNE_DECISION_MFMA = 7 };
 int32_t ldpc_fd_set_tuning(ldpc_fd_code code, int32_t key, int32_t value);
 int32_t ldpc_fd_get_tuning(ldpc_fd_code code, int32_t key, int32_t *value);
 

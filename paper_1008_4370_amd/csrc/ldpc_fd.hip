@@ -43,6 +43,9 @@ struct ldpc_fd_code_s {
   int tail_logr = 2, tail_frames = 128;
   // 1: the fused pass evaluates the variable node in FP64 (see conv_prior_d)
   int precise = 0;
+  // 1: the tentative decision's transforms on the matrix cores (FP16 MFMA,
+  // variants with 16 frames per wavefront)
+  int mfma = 0;
   int device = 0;
   std::vector<void*> allocs;
   DevCode dev{};
@@ -126,14 +129,22 @@ struct Impl {
   template <typename S>
   static void fused(const DevCode& cd, int Fmax, const float* prior, S* buf0, S* buf1, uint8_t* hard, uint8_t* fsw,
                     const int* alist, const int* nact, const int* rnd, const int* maxit, int maxit_all, int cap,
-                    bool precise, hipStream_t s) {
+                    bool precise, bool mfma, hipStream_t s) {
     if (Fmax == 0) return;
+    const dim3 grid(fused_blocks(cd, Fmax, cap)), block(64 * kWaves);
+    if constexpr (kMfmaDecision<G>) {
+      if (mfma && !precise) {
+        hipLaunchKernelGGL((k_fused<G, KMAX, S, false, true>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
+                           alist, nact, rnd, maxit, maxit_all);
+        return;
+      }
+    }
     if (precise)
-      hipLaunchKernelGGL((k_fused<G, KMAX, S, true>), dim3(fused_blocks(cd, Fmax, cap)), dim3(64 * kWaves), lds(), s,
-                         cd, prior, buf0, buf1, hard, fsw, alist, nact, rnd, maxit, maxit_all);
+      hipLaunchKernelGGL((k_fused<G, KMAX, S, true, false>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
+                         alist, nact, rnd, maxit, maxit_all);
     else
-      hipLaunchKernelGGL((k_fused<G, KMAX, S, false>), dim3(fused_blocks(cd, Fmax, cap)), dim3(64 * kWaves), lds(), s,
-                         cd, prior, buf0, buf1, hard, fsw, alist, nact, rnd, maxit, maxit_all);
+      hipLaunchKernelGGL((k_fused<G, KMAX, S, false, false>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
+                         alist, nact, rnd, maxit, maxit_all);
   }
 };
 
@@ -507,13 +518,13 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
       using I = decltype(impl);
       if (prec == LDPC_FD_FP32)
         I::template fused<float>(cd, F, w.prior, (float*)w.buf[0], (float*)w.buf[1], hard, w.fsw, w.alist, w.nact,
-                                 w.rnd, nullptr, max_iter, c->blocks, c->precise, st);
+                                 w.rnd, nullptr, max_iter, c->blocks, c->precise, c->mfma, st);
       else if (prec == LDPC_FD_FP16)
         I::template fused<_Float16>(cd, F, w.prior, (_Float16*)w.buf[0], (_Float16*)w.buf[1], hard, w.fsw, w.alist,
-                                    w.nact, w.rnd, nullptr, max_iter, c->blocks, c->precise, st);
+                                    w.nact, w.rnd, nullptr, max_iter, c->blocks, c->precise, c->mfma, st);
       else
         I::template fused<bf16_t>(cd, F, w.prior, (bf16_t*)w.buf[0], (bf16_t*)w.buf[1], hard, w.fsw, w.alist,
-                                  w.nact, w.rnd, nullptr, max_iter, c->blocks, c->precise, st);
+                                  w.nact, w.rnd, nullptr, max_iter, c->blocks, c->precise, c->mfma, st);
     });
     if (e1) (void)hipEventRecord(e1, st);
     launch_syndrome_retire(c, F, hard, w.fsw, synd, w.unsat, w.mism, w.alist, w.nact, w.rnd, max_iter, nullptr, w.tmp,
@@ -663,9 +674,9 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
           if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, in, n_msg / 4);
         }
         if (c2v_in)
-          I::template fused<S>(cd, F, prior, out, in, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise, s);
+          I::template fused<S>(cd, F, prior, out, in, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise, c->mfma, s);
         else
-          I::template fused<S>(cd, F, prior, nullptr, out, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise, s);
+          I::template fused<S>(cd, F, prior, nullptr, out, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise, c->mfma, s);
         if (prec != LDPC_FD_FP32)
           hipLaunchKernelGGL((k_convert<S, float>), dim3(g), dim3(256), 0, s, (const S*)out, c2v_out, n_msg / 4);
       };
@@ -722,6 +733,10 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
       if (value != 0 && value != 1) return fail(LDPC_FD_E_INVALID, "precise: 0 or 1");
       c->precise = value;
       return LDPC_FD_OK;
+    case LDPC_FD_TUNE_DECISION_MFMA:
+      if (value != 0 && value != 1) return fail(LDPC_FD_E_INVALID, "decision MFMA: 0 or 1");
+      c->mfma = value;
+      return LDPC_FD_OK;
     default:
       return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
@@ -737,6 +752,7 @@ int32_t ldpc_fd_get_tuning(ldpc_fd_code c, int32_t key, int32_t* value) {
     case LDPC_FD_TUNE_TAIL_ENTRIES: *value = 1 << c->tail_logr; return LDPC_FD_OK;
     case LDPC_FD_TUNE_TAIL_FRAMES: *value = c->tail_frames; return LDPC_FD_OK;
     case LDPC_FD_TUNE_PRECISE: *value = c->precise; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_DECISION_MFMA: *value = c->mfma; return LDPC_FD_OK;
     default: return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
 }

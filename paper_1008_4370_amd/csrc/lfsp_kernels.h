@@ -82,6 +82,128 @@ __device__ __forceinline__ void decide(const float (&Y)[G::R], float (&Xo)[G::R]
   __builtin_amdgcn_wave_barrier();
 }
 
+// ---- tentative decision on the matrix cores ------------------------------------
+// For the geometry with 4 lanes per frame (16 frames per wavefront, q = 16, 32,
+// 64) the three Hadamard transforms of the decision run as FP16 MFMAs with
+// FP32 accumulation: the wave's 16 frames are the N columns of a
+// 16x16x16 product, H_q = H_{q/16} (x) H_16 splits into one MFMA with H_16
+// per block of 16 entries and a butterfly over the q/16 blocks (VALU, FP32).
+// Operand layout of v_mfma_f32_16x16x16f16 (lane l, c = 0..3): A[l % 16][4 (l / 16) + c],
+// B[4 (l / 16) + c][l % 16], D[4 (l / 16) + c][l % 16].  A is H_16; a frame's
+// vector enters as B through the frame rows in LDS (lane l reads frame l % 16,
+// entries 16 b + 4 (l / 16) + c: one 16-byte read per block), and D has the
+// layout of B, so the product of two transforms feeds the third directly.
+// Inputs are FP16 pairs (hi, lo) holding ~22 bits of each FP32 value; Y is
+// scaled to max |Y| = 1 and |Xo| <= 1 make every transform fit, with the
+// product scaled by 1/q before the last one.  Only the signs of Q are used.
+typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ h4_t h16_frag() {
+  const int l = lane_id(), i = l & 15, k0 = (l >> 4) << 2;
+  h4_t a;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) a[c] = (__builtin_popcount(i & (k0 + c)) & 1) ? (_Float16)-1.0f : (_Float16)1.0f;
+  return a;
+}
+
+template <int NB>
+__device__ __forceinline__ void wht_blocks(f4_t (&g)[NB]) {
+#pragma unroll
+  for (int s = 1; s < NB; s <<= 1)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      if (!(b & s)) {
+        const f4_t x = g[b], y = g[b | s];
+        g[b] = x + y;
+        g[b | s] = x - y;
+      }
+}
+
+// An FP32 quadruple as two FP16 operands, x = hi + lo * 2^-11 (lo scaled up
+// so that it stays clear of the FP16 subnormal range): H_16 x = H_16 hi +
+// 2^-11 H_16 lo keeps about 22 bits of x, with FP32 accumulation.
+__device__ __forceinline__ f4_t mfma_h16_split(h4_t H, f4_t x) {
+  const f4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  h4_t hi, lo;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    hi[c] = (_Float16)x[c];
+    lo[c] = (_Float16)((x[c] - (float)hi[c]) * 2048.0f);
+  }
+  const f4_t a = __builtin_amdgcn_mfma_f32_16x16x16f16(H, hi, zero, 0, 0, 0);
+  const f4_t b = __builtin_amdgcn_mfma_f32_16x16x16f16(H, lo, zero, 0, 0, 0);
+  return a + b * (1.0f / 2048.0f);
+}
+
+// Transform of one LDS-resident vector per frame: H_16 on each block of 16
+// entries (read from the frame rows as MFMA B operands, one block at a time to
+// keep few registers live), then the butterfly over the blocks.
+template <class G>
+__device__ __forceinline__ void mfma_wht_rows(const float* lds, int rbn, int cfn, int g4, h4_t H,
+                                              f4_t (&t)[G::Q / 16]) {
+#pragma unroll
+  for (int b = 0; b < G::Q / 16; ++b) {
+    const float4 v = *reinterpret_cast<const float4*>(lds + (rbn | ((16 * b + g4) ^ cfn)));
+    t[b] = mfma_h16_split(H, f4_t{v.x, v.y, v.z, v.w});
+  }
+  wht_blocks<G::Q / 16>(t);
+}
+
+template <class G>
+__device__ __forceinline__ void decide_mfma(const float (&Y)[G::R], const float (&Xo)[G::R], float* lds, int rb,
+                                            int cf, int zl, uint64_t cols_a, uint64_t cols_b, int& hard, int& fa,
+                                            int& fb) {
+  static_assert(G::L == 4 && G::Q >= 16 && G::Q <= 64, "MFMA decision needs 16 frames per wave");
+  constexpr int NB = G::Q / 16;
+  const int l = lane_id(), n = l & 15, g4 = (l >> 4) << 2;
+  // row of frame n of this wave (rows of a wave are T * QP = 16 Q floats apart)
+  const int rbn = (rb & ~(G::T * G::QP - 1)) | (n * G::QP), cfn = G::swz(n);
+  const h4_t H = h16_frag();
+  f4_t ty[NB], tq[NB];
+  // Y scaled to max |Y| = 1 over the frame (its 4 lanes form a quad): where
+  // the channel and the message disagree all of Y can lie below the FP16
+  // range.  Xo needs no scaling (|Xo| <= Xo(0) = 1).
+  float ys[G::R];
+  float mx = 0.0f;
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) mx = __builtin_fmaxf(mx, __builtin_fabsf(Y[r]));
+  mx = __builtin_fmaxf(mx, lane_xor(mx, 1));
+  mx = __builtin_fmaxf(mx, lane_xor(mx, 2));
+  const float inv = mx > 0.0f ? 1.0f / mx : 1.0f;
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) ys[r] = Y[r] * inv;
+  __builtin_amdgcn_wave_barrier();
+  lds_put<G>(lds, rb, cf, zl, ys);
+  __builtin_amdgcn_wave_barrier();
+  mfma_wht_rows<G>(lds, rbn, cfn, g4, H, ty);
+  __builtin_amdgcn_wave_barrier();
+  lds_put<G>(lds, rb, cf, zl, Xo);
+  __builtin_amdgcn_wave_barrier();
+  mfma_wht_rows<G>(lds, rbn, cfn, g4, H, tq);
+  // product (scaled by 1/q to stay in FP16 range), then the third transform
+#pragma unroll
+  for (int b = 0; b < NB; ++b) tq[b] = mfma_h16_split(H, ty[b] * tq[b] * (1.0f / G::Q));
+  wht_blocks<NB>(tq);
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+    *reinterpret_cast<float4*>(lds + (rbn | ((16 * b + g4) ^ cfn))) = make_float4(tq[b][0], tq[b][1], tq[b][2], tq[b][3]);
+  __builtin_amdgcn_wave_barrier();
+  hard = 0; fa = 0; fb = 0;
+  const int rcf = rb | cf;
+#pragma unroll
+  for (int i = 0; i < G::LOGQ; ++i) {
+    hard |= (lds[rcf ^ (1 << i)] < 0.0f) << i;
+    fa |= (lds[rcf ^ (int)((cols_a >> (8 * i)) & 0xFF)] < 0.0f) << i;
+    fb |= (lds[rcf ^ (int)((cols_b >> (8 * i)) & 0xFF)] < 0.0f) << i;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <class G>
+constexpr bool kMfmaDecision = G::L == 4 && G::Q >= 16 && G::Q <= 64;
+
 // Lambda_vc = Gamma(Y / Y(0)) in place (normalisation P_vc(0) = 1).
 template <class G>
 __device__ __forceinline__ void normalise_gamma(float (&v)[G::R]) {
@@ -270,7 +392,8 @@ __device__ __forceinline__ void issue_edge(const DevCode& cd, const float* __res
 
 // P (precise): the variable node in FP64 (prior factors given as signed
 // complements, see conv_prior_d).
-template <class G, int KMAX, typename S, bool P>
+// DM: the decision's transforms on the matrix cores (decide_mfma).
+template <class G, int KMAX, typename S, bool P, bool DM>
 __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __restrict__ tp, S* __restrict__ buf0,
                                            S* __restrict__ buf1, uint8_t* __restrict__ hard,
                                            uint8_t* __restrict__ fsw, int f, bool valid, const FrameState& fs,
@@ -322,7 +445,10 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
         for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
         int hd, fa, fo;
         const int ho = uni(cd.e_label[eo]);
-        decide<G>(st[j], xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
+        if constexpr (DM)
+          decide_mfma<G>(st[j], xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
+        else
+          decide<G>(st[j], xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
         if (valid && fs.decide && zl == 0) {
           hard[(size_t)f * cd.N + v] = (uint8_t)hd;
           fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
@@ -373,8 +499,10 @@ constexpr int kXcds = 8;
 // workgroups of XCD g % 8, so both reads of a message within a pass (as the
 // other edge of its variable, and by its own check at the owner visit) come
 // from the same XCD's L2.  gridDim.x must be a multiple of 8.
-template <class G, int KMAX, typename S, bool P>
-__global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restrict__ tp, S* __restrict__ buf0,
+// At least 2 wavefronts per SIMD (<= 256 VGPRs): the stash of a check's
+// messages is the largest register consumer.
+template <class G, int KMAX, typename S, bool P, bool DM>
+__global__ __launch_bounds__(256, 2) void k_fused(DevCode cd, const float* __restrict__ tp, S* __restrict__ buf0,
                                                S* __restrict__ buf1, uint8_t* __restrict__ hard,
                                                uint8_t* __restrict__ fsw, const int* __restrict__ alist,
                                                const int* __restrict__ nact_p, const int* __restrict__ rnd,
@@ -397,7 +525,7 @@ __global__ __launch_bounds__(256) void k_fused(DevCode cd, const float* __restri
     const bool valid = slot < nact;
     const int f = alist[valid ? slot : nact - 1];
     const FrameState fs = frame_state(rnd, maxit, maxit_all, f);
-    fused_item<G, KMAX, S, P>(cd, tp, buf0, buf1, hard, fsw, f, valid, fs, c, lds, rb, cf, zl);
+    fused_item<G, KMAX, S, P, DM>(cd, tp, buf0, buf1, hard, fsw, f, valid, fs, c, lds, rb, cf, zl);
   }
 }
 

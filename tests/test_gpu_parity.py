@@ -313,3 +313,55 @@ def test_precise_variable_node_when_channel_and_messages_disagree():
     assert errs[1] < TOL_FP32
     assert errs[1] <= errs[0]
     gcode.close()
+
+
+MFMA_CASES = [CASES[2], CASES[4], CASES[5]]   # q = 16, 32, 64 with 4 lanes per frame
+
+
+@pytest.mark.parametrize("case", MFMA_CASES, ids=lambda c: c[0])
+def test_decision_on_matrix_cores(case):
+    """Decision transforms as FP16 MFMAs (tuning key DECISION_MFMA): the messages
+    are bit-identical to the VALU decision's round (the decision does not feed
+    them); hard decisions equal the oracle's except bits whose posterior value
+    is within FP16 reach of a tie (|q| < 1e-2), and at most 1% of symbols differ."""
+    name, m, k, N, F, ebn0 = case
+    print(f"[case] mfma decision {name} F={F}", flush=True)
+    code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0)
+    gcode = D.Code.from_synth(code)
+    gcode.set_tuning(lane_entries=(1 << m) // 4)
+    L = _dev(llr)
+    c2vs, _, decs = run_rounds(tc, llr.astype(np.float64), 3)
+    for i in (0, 1):
+        st = _dev(to_state(c2vs[i]))
+        gcode.set_tuning(decision_mfma=0)
+        base = D.round_step(gcode, L, st, "fused")
+        gcode.set_tuning(decision_mfma=1)
+        out = D.round_step(gcode, L, st, "fused")
+        torch.cuda.synchronize()
+        assert torch.equal(out["c2v"], base["c2v"])
+        hard = out["hard"].cpu().numpy()
+        d = decs[i]
+        tie = (np.abs(d.qbits) < 1e-2).any(-1)
+        assert np.array_equal(hard[~tie], d.hard[~tie])
+        assert (hard == d.hard).mean() >= 0.99
+        assert np.array_equal(out["synd"].cpu().numpy().astype(np.int64), enc.syndrome(hard.astype(np.int64)))
+    gcode.close()
+
+
+def test_decision_on_matrix_cores_full_decode():
+    """Full decodes with the MFMA decision stop at the same round with the same
+    output as the VALU decision for >= 98% of frames (GF(64) N=60, 2.5 dB)."""
+    name, m, k, N, F, ebn0 = CASES[5]
+    code, enc, cw, llr, tc = _setup(m, k, N, 256, ebn0)
+    gcode = D.Code.from_synth(code)
+    gcode.set_tuning(lane_entries=16)
+    L = _dev(llr)
+    res = []
+    for mf in (0, 1):
+        gcode.set_tuning(decision_mfma=mf)
+        r = D.decode(gcode, L, 50, prec="fp32", mode="fused")
+        res.append({k2: v.cpu().numpy() for k2, v in r.items()})
+    same = (res[0]["iters"] == res[1]["iters"]) & (res[0]["hard"] == res[1]["hard"]).all(1)
+    print(f"  identical frames {same.mean():.3f}", flush=True)
+    assert same.mean() >= 0.98
+    gcode.close()
