@@ -61,6 +61,35 @@ def cpu_baseline(batch, max_iter, frames_per_worker=2, workers=None):
                        f"{workers} processes x 1 thread, {wall:.1f} s wall"), res
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fused_gf64_n1000_fp32_traffic.json")
+
+
+def source_sha256():
+    """Hash of the library sources (kernels, host code, C-ABI header)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1008_4370_amd", "csrc", "*")))
+    for f in files + [os.path.join(ROOT, "include", "ldpc_fd.h")]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_fused launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (copy-calibrated), or None when the library sources have
+    changed since they were taken."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    with open(TRAFFIC_PROFILE) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256") != source_sha256():
+        return None
+    return t
+
+
 def alg_bytes(code, iters, s, first_pass=True):
     """Algorithmic HBM bytes of all fused-pass launches for one decode."""
     E, N, q, m = code.E, code.N, code.q, code.m
@@ -316,6 +345,19 @@ def main():
         total_bytes = int(np.sum(iters)) * 4 * E * q * 4 * args.steps
         achieved = total_bytes / ((kms + ms_var) / 1e3) / 1e9
         roof_kernel = "k_check_plain+k_var_plain"
+    # measured HBM bytes per k_fused launch (committed counters) for this exact
+    # configuration: default workload, FP32 storage, fused, tuned defaults
+    traffic, traffic_note = None, "no counters for this configuration"
+    if (args.workload == "gf64_n1000" and args.prec == "fp32" and args.mode == "fused" and not args.precise
+            and not tune and args.point == 2 and args.max_iter == 100):
+        t = measured_traffic()
+        if t is None:
+            traffic_note = "kernel sources changed since the counters were taken"
+        else:
+            traffic = int(round(t["traffic_bytes_per_launch"]))
+            traffic_note = (f"HBM bytes per launch from FETCH_SIZE x {t['fetch_factor']:.3f} + WRITE_SIZE x "
+                            f"{t['write_factor']:.3f} (KiB, copy-calibrated), mean of {t['launches']} launches of one "
+                            f"decode; algorithmic {int(round(t['alg_bytes_per_launch']))} bytes per launch")
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -342,13 +384,14 @@ def main():
             "autotuned": tuned and not tune,
         },
         "roofline": None if achieved is None else {
+            "traffic": traffic,
+            "traffic_note": traffic_note,
             "bound": "hbm",
             "kernel": roof_kernel,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
             "launches": int(launches),
             "kernel_ms_per_step": round(kms / args.steps, 4),
         },
