@@ -234,6 +234,9 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *     the variant with TAIL_ENTRIES entries per lane (default 4): with few
  *     frames left a pass is bound by one check's latency, which more lanes
  *     per frame shorten.  TAIL_FRAMES = 0 keeps one variant throughout.
+ *   LDPC_FD_TUNE_TAIL_SPLIT: 1 (default) = those chunks run the edge-parallel
+ *     pass, one wavefront per edge of a check (identical results); 0 = the
+ *     check-serial pass with the tail variant.
  *   LDPC_FD_TUNE_PRECISE: 1 = the FUSED pass evaluates the variable node (prior
  *     convolution and normalisation, Sec. 3.2 VARIABLE TO CHECK) in FP64 from the
  *     stored words, with 1 - |P| and 1 - |tanh(L/2)| carried at FP32 relative
@@ -250,7 +253,7 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  * Errors: E_INVALID (unknown key or value), E_UNSUPPORTED (no such variant). */
 enum { LDPC_FD_TUNE_LANE_ENTRIES = 0, LDPC_FD_TUNE_GRID_BLOCKS = 1, LDPC_FD_TUNE_CHUNK = 2,
        LDPC_FD_TUNE_GRAPHS = 3, LDPC_FD_TUNE_TAIL_ENTRIES = 4, LDPC_FD_TUNE_TAIL_FRAMES = 5,
-       LDPC_FD_TUNE_PRECISE = 6, LDPC_FD_TUNE_DECISION_MFMA = 7 };
+       LDPC_FD_TUNE_PRECISE = 6, LDPC_FD_TUNE_DECISION_MFMA = 7, LDPC_FD_TUNE_TAIL_SPLIT = 8 };
 int32_t ldpc_fd_set_tuning(ldpc_fd_code code, int32_t key, int32_t value);
 int32_t ldpc_fd_get_tuning(ldpc_fd_code code, int32_t key, int32_t *value);
 

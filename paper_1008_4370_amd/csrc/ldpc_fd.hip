@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <type_traits>
+
 #include "ldpc_fd.h"
 #include "lfsp_kernels.h"
 
@@ -41,6 +43,8 @@ struct ldpc_fd_code_s {
   // chunks that start with at most tail_frames active frames use the variant
   // with 2^tail_logr entries per lane (shorter per-item latency)
   int tail_logr = 2, tail_frames = 128;
+  // 1: such chunks run the edge-parallel pass (k_fused_split)
+  int split = 1;
   // 1: the fused pass evaluates the variable node in FP64 (see conv_prior_d)
   int precise = 0;
   // 1: the tentative decision's transforms on the matrix cores (FP16 MFMA,
@@ -125,6 +129,23 @@ struct Impl {
     long b = std::min<long>(blocks(items), cap);
     b = (b + kXcds - 1) / kXcds * kXcds;
     return (unsigned)std::max<long>(b, kXcds);
+  }
+  // Edge-parallel pass (k_fused_split) over at most Fmax active frames: one
+  // workgroup of KMAX wavefronts per (frame group, check), grid-stride.
+  template <typename S>
+  static void fused_split(const DevCode& cd, int Fmax, const float* prior, S* buf0, S* buf1, uint8_t* hard,
+                          uint8_t* fsw, const int* alist, const int* nact, const int* rnd, const int* maxit,
+                          int maxit_all, bool precise, hipStream_t s) {
+    if (Fmax == 0) return;
+    const long items = (long)((Fmax + G::T - 1) / G::T) * cd.M;
+    const dim3 grid((unsigned)std::min<long>(items, 65536)), block(64 * KMAX);
+    const size_t lds_bytes = (size_t)2 * KMAX * G::T * G::QP * sizeof(float);
+    if (precise)
+      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, true>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
+                         fsw, alist, nact, rnd, maxit, maxit_all);
+    else
+      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, false>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
+                         fsw, alist, nact, rnd, maxit, maxit_all);
   }
   template <typename S>
   static void fused(const DevCode& cd, int Fmax, const float* prior, S* buf0, S* buf1, uint8_t* hard, uint8_t* fsw,
@@ -516,15 +537,21 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
     if (e0) (void)hipEventRecord(e0, st);
     ok = dispatch(c->m, c->kmax, lr, [&](auto impl) {
       using I = decltype(impl);
+      auto run = [&](auto* b0, auto* b1) {
+        using S = std::remove_pointer_t<decltype(b0)>;
+        if (tail && c->split)
+          I::template fused_split<S>(cd, std::min(F, std::max(c->tail_frames, 1)), w.prior, b0, b1, hard, w.fsw,
+                                     w.alist, w.nact, w.rnd, nullptr, max_iter, c->precise, st);
+        else
+          I::template fused<S>(cd, F, w.prior, b0, b1, hard, w.fsw, w.alist, w.nact, w.rnd, nullptr, max_iter,
+                               c->blocks, c->precise, c->mfma, st);
+      };
       if (prec == LDPC_FD_FP32)
-        I::template fused<float>(cd, F, w.prior, (float*)w.buf[0], (float*)w.buf[1], hard, w.fsw, w.alist, w.nact,
-                                 w.rnd, nullptr, max_iter, c->blocks, c->precise, c->mfma, st);
+        run((float*)w.buf[0], (float*)w.buf[1]);
       else if (prec == LDPC_FD_FP16)
-        I::template fused<_Float16>(cd, F, w.prior, (_Float16*)w.buf[0], (_Float16*)w.buf[1], hard, w.fsw, w.alist,
-                                    w.nact, w.rnd, nullptr, max_iter, c->blocks, c->precise, c->mfma, st);
+        run((_Float16*)w.buf[0], (_Float16*)w.buf[1]);
       else
-        I::template fused<bf16_t>(cd, F, w.prior, (bf16_t*)w.buf[0], (bf16_t*)w.buf[1], hard, w.fsw, w.alist,
-                                  w.nact, w.rnd, nullptr, max_iter, c->blocks, c->precise, c->mfma, st);
+        run((bf16_t*)w.buf[0], (bf16_t*)w.buf[1]);
     });
     if (e1) (void)hipEventRecord(e1, st);
     launch_syndrome_retire(c, F, hard, w.fsw, synd, w.unsat, w.mism, w.alist, w.nact, w.rnd, max_iter, nullptr, w.tmp,
@@ -737,6 +764,10 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
       if (value != 0 && value != 1) return fail(LDPC_FD_E_INVALID, "decision MFMA: 0 or 1");
       c->mfma = value;
       return LDPC_FD_OK;
+    case LDPC_FD_TUNE_TAIL_SPLIT:
+      if (value != 0 && value != 1) return fail(LDPC_FD_E_INVALID, "tail split: 0 or 1");
+      c->split = value;
+      return LDPC_FD_OK;
     default:
       return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
@@ -753,6 +784,7 @@ int32_t ldpc_fd_get_tuning(ldpc_fd_code c, int32_t key, int32_t* value) {
     case LDPC_FD_TUNE_TAIL_FRAMES: *value = c->tail_frames; return LDPC_FD_OK;
     case LDPC_FD_TUNE_PRECISE: *value = c->precise; return LDPC_FD_OK;
     case LDPC_FD_TUNE_DECISION_MFMA: *value = c->mfma; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_TAIL_SPLIT: *value = c->split; return LDPC_FD_OK;
     default: return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
 }

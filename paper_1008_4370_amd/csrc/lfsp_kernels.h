@@ -529,6 +529,124 @@ __global__ __launch_bounds__(256, 2) void k_fused(DevCode cd, const float* __res
   }
 }
 
+// Pass with few active frames: one workgroup of KMAX wavefronts per (group of
+// T frames, check), wavefront j taking edge j.  Each computes its
+// variable-to-check message (and, on owner visits, the decision) in parallel,
+// leaves it in check coordinates in LDS, and after a barrier every wavefront
+// sums the check's magnitudes in edge order (the order of fused_item, so the
+// results are bit-identical to k_fused) and forms its own extrinsic output.
+// A check's latency is then one edge instead of k.  LDS: per wavefront T rows
+// of Q floats for the label permutations, and the stash [KMAX][T][Q].
+template <class G, int KMAX, typename S, bool P>
+__global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const float* __restrict__ tp,
+                                                           S* __restrict__ buf0, S* __restrict__ buf1,
+                                                           uint8_t* __restrict__ hard, uint8_t* __restrict__ fsw,
+                                                           const int* __restrict__ alist,
+                                                           const int* __restrict__ nact_p,
+                                                           const int* __restrict__ rnd,
+                                                           const int* __restrict__ maxit, int maxit_all) {
+  extern __shared__ float lds[];
+  float* stash = lds + KMAX * G::T * G::QP;
+  const int j = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nact = *nact_p;
+  const int groups = (nact + G::T - 1) / G::T;
+  const long items = (long)groups * cd.M;
+  const int fl = lane / G::L, zl = lane % G::L;
+  const int rb = (j * G::T + fl) * G::QP, cf = G::swz(fl);
+  using Acc = typename std::conditional<P, double, float>::type;
+  for (long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int g = (int)(it / cd.M), c = (int)(it % cd.M);
+    const int slot = g * G::T + fl;
+    const bool valid = slot < nact;
+    const int f = alist[valid ? slot : nact - 1];
+    const FrameState fs = frame_state(rnd, maxit, maxit_all, f);
+    const int e0 = uni(cd.row_ptr[c]), deg = uni(cd.row_ptr[c + 1]) - e0;
+    const size_t fb = (size_t)f * cd.E * G::Q;
+    const S* cin = (fs.ell & 1) ? buf1 : buf0;
+    S* cout = (fs.ell & 1) ? buf0 : buf1;
+    const bool any_decide = __builtin_amdgcn_ballot_w64(fs.decide && valid) != 0;
+    const bool any_write = __builtin_amdgcn_ballot_w64(fs.write && valid) != 0;
+    float st[G::R];
+    if (j < deg) {
+      const int e = e0 + j;
+      EdgeLoads<G, S> cur;
+      issue_edge<G, S>(cd, tp, cin, fb, f, e, fs, any_decide, zl, cur);
+      const int v = uni(cd.e_var[e]);
+      const int eo = uni(cd.e_other[e]);
+      const int h = uni(cd.e_label[e]);
+      float t[G::LOGQ];
+#pragma unroll
+      for (int i = 0; i < G::LOGQ; ++i) t[i] = cur.l[i];
+      double y64[P ? G::R : 1];
+      if constexpr (P) {
+#pragma unroll
+        for (int r = 0; r < G::R; ++r) y64[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0 : 0.0) : gamma_inv_d(cur.x[r]);
+        conv_prior_d<G>(y64, t);
+#pragma unroll
+        for (int r = 0; r < G::R; ++r) st[r] = (float)y64[r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < G::R; ++r) st[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
+        conv_prior<G>(st, t);
+      }
+      if (any_decide && e < eo) {
+        float xo[G::R];
+#pragma unroll
+        for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
+        int hd, fa, fo;
+        const int ho = uni(cd.e_label[eo]);
+        decide<G>(st, xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
+        if (valid && fs.decide && zl == 0) {
+          hard[(size_t)f * cd.N + v] = (uint8_t)hd;
+          fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
+          fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
+        }
+      }
+      if constexpr (P)
+        normalise_gamma_d<G>(y64, st);
+      else
+        normalise_gamma<G>(st);
+      permute<G>(st, lds, rb, cf, zl, uni64(cd.colsT[h]));
+      lds_put<G>(stash, rb, cf, zl, st);
+    }
+    __syncthreads();
+    if (j < deg && any_write) {
+      Acc smag[G::R];
+      uint32_t ssgn[G::R];
+#pragma unroll
+      for (int r = 0; r < G::R; ++r) {
+        smag[r] = 0;
+        ssgn[r] = 0u;
+      }
+      for (int i = 0; i < deg; ++i) {
+        const int rbi = (i * G::T + fl) * G::QP;
+#pragma unroll
+        for (int h4 = 0; h4 < G::R / 4; ++h4) {
+          const int z0 = (zl << 2) | (h4 << (2 + G::LOGL));
+          const float4 w = *reinterpret_cast<const float4*>(stash + (rbi | (z0 ^ cf)));
+          const float ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int q4 = 0; q4 < 4; ++q4) {
+            smag[4 * h4 + q4] += (Acc)__builtin_fabsf(ww[q4]);
+            ssgn[4 * h4 + q4] ^= __float_as_uint(ww[q4]);
+          }
+        }
+      }
+      const int e = e0 + j;
+      const int hinv = uni(cd.ginv[cd.e_label[e]]);
+      float o[G::R];
+#pragma unroll
+      for (int r = 0; r < G::R; ++r) {
+        const float mag = __builtin_amdgcn_fmed3f((float)(smag[r] - (Acc)__builtin_fabsf(st[r])), 0.0f, kLmax);
+        o[r] = __uint_as_float(((ssgn[r] ^ __float_as_uint(st[r])) & 0x80000000u) | __float_as_uint(mag));
+      }
+      permute<G>(o, lds, rb, cf, zl, uni64(cd.colsT[hinv]));
+      if (valid && fs.write) store_msg<G, S>(cout + fb + (size_t)e * G::Q, zl, o);
+    }
+    __syncthreads();  // the stash is rewritten by the next item
+  }
+}
+
 // Syndromes of the tentative decision, for codes whose rows do not fit in LDS
 // (one thread per (active frame, check)): direct s_c = sum_{v in V_c} h_cv x^_v
 // and Fourier word = XOR of per-edge sign words.  Flags the frame when either

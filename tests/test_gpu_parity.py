@@ -365,3 +365,28 @@ def test_decision_on_matrix_cores_full_decode():
     print(f"  identical frames {same.mean():.3f}", flush=True)
     assert same.mean() >= 0.98
     gcode.close()
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[5], CASES[8]], ids=lambda c: c[0])
+@pytest.mark.parametrize("precise", [0, 1])
+def test_edge_parallel_tail_pass_is_identical(case, precise):
+    """Chunks with few active frames run the edge-parallel pass (one wavefront
+    per edge); it sums a check's magnitudes in the same order as the
+    check-serial pass, so decodes are bit-identical with it on and off (forced
+    here for every chunk by a large tail threshold)."""
+    name, m, k, N, F, ebn0 = case
+    print(f"[case] split tail {name} precise={precise} F={F}", flush=True)
+    code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0)
+    gcode = D.Code.from_synth(code)
+    gcode.set_tuning(tail_frames=1 << 20, tail_entries=4, precise=precise, chunk=3)
+    L = _dev(llr)
+    res = []
+    for split in (0, 1):
+        gcode.set_tuning(tail_split=split)
+        for prec in ("fp32", "fp16"):
+            r = D.decode(gcode, L, 30, prec=prec, mode="fused")
+            res.append({k2: v.cpu().numpy() for k2, v in r.items()})
+    for a, b in ((res[0], res[2]), (res[1], res[3])):
+        for key in ("hard", "synd", "iters", "status"):
+            assert np.array_equal(a[key], b[key]), key
+    gcode.close()
