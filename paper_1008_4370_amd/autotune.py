@@ -38,7 +38,7 @@ def key(code: D.Code, prec: str, frames: int) -> str:
 def lane_choices(m: int, kmax: int):
     q = 1 << m
     out = [4]
-    if kmax <= 8 and q >= 8:
+    if kmax <= 16 and q >= 8:
         out.append(8)
     if kmax <= 8 and 16 <= q <= 128:
         out.append(16)
@@ -78,7 +78,7 @@ def _time_decode(dec, llr, max_iter, reps):
 
 
 def tune(code: D.Code, llr, prec: str = "fp32", max_iter: int = 100, reps: int = 3,
-         grid_blocks=(2048, 4096, 8192, 16384, 32768), chunks=(4, 8), tail_frames=(0, 32, 128, 512),
+         grid_blocks=(2048, 4096, 8192, 16384, 32768), chunks=(4, 8), tail_frames=(0, 32, 128, 512, 2048, 1 << 20),
          path: str | None = TABLE, log=None) -> dict:
     """Sweep the launch choices for decoding `llr` (device [F][N][m]) and record
     the best: first the main variant, grid and chunk (tail variant at its

@@ -171,7 +171,7 @@ struct Impl {
 
 // Kernel variant: rows of weight <= 8 have variants with 4, 8 or 16 entries
 // per lane (log2 R = 2, 3, 4; 16 entries only for q <= 128, where the kernel
-// keeps its stash in registers); rows of weight 9..16 use 4 entries per lane.
+// keeps its stash in registers); rows of weight 9..16 use 4 or 8.
 template <int LOGQ, class Fn>
 bool dispatch_q(int kmax, int logr, Fn&& fn) {
   if (kmax <= 8) {
@@ -185,6 +185,9 @@ bool dispatch_q(int kmax, int logr, Fn&& fn) {
     return true;
   }
   if (kmax <= 16) {
+    if constexpr (LOGQ >= 3) {
+      if (logr == 3) { fn(Impl<LOGQ, 3, 16>{}); return true; }
+    }
     fn(Impl<LOGQ, 2, 16>{});
     return true;
   }
@@ -730,7 +733,7 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
   switch (key) {
     case LDPC_FD_TUNE_LANE_ENTRIES:
       if (value != 4 && value != 8 && value != 16) return fail(LDPC_FD_E_INVALID, "entries per lane: 4, 8 or 16");
-      if (value > c->q || (value == 16 && c->m == 8) || (value > 4 && c->kmax > 8))
+      if (value > c->q || (value == 16 && c->m == 8) || (value > 8 && c->kmax > 8))
         return fail(LDPC_FD_E_UNSUPPORTED, "no kernel variant with that many entries per lane for this code");
       c->logr = value == 4 ? 2 : value == 8 ? 3 : 4;
       return LDPC_FD_OK;
@@ -748,7 +751,7 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
       return LDPC_FD_OK;
     case LDPC_FD_TUNE_TAIL_ENTRIES:
       if (value != 4 && value != 8 && value != 16) return fail(LDPC_FD_E_INVALID, "entries per lane: 4, 8 or 16");
-      if (value > c->q || (value == 16 && c->m == 8) || (value > 4 && c->kmax > 8))
+      if (value > c->q || (value == 16 && c->m == 8) || (value > 8 && c->kmax > 8))
         return fail(LDPC_FD_E_UNSUPPORTED, "no kernel variant with that many entries per lane for this code");
       c->tail_logr = value == 4 ? 2 : value == 8 ? 3 : 4;
       return LDPC_FD_OK;

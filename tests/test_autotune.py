@@ -21,7 +21,8 @@ def test_key_and_lane_choices():
     assert autotune.lane_choices(3, 4) == [4, 8]
     assert autotune.lane_choices(6, 7) == [4, 8, 16]
     assert autotune.lane_choices(8, 8) == [4, 8]
-    assert autotune.lane_choices(8, 16) == [4]
+    assert autotune.lane_choices(8, 16) == [4, 8]
+    assert autotune.lane_choices(2, 16) == [4]
 
 
 def test_committed_table_is_valid():

@@ -36,11 +36,17 @@ def _drain(pool, ncodes, results, max_steps=400):
     raise AssertionError("pool did not drain")
 
 
+@pytest.mark.parametrize("tail", ["tail", "full"])
 @pytest.mark.parametrize("prec", ["fp32", "fp16"])
-def test_alone_equals_in_the_mix(prec):
+def test_alone_equals_in_the_mix(prec, tail):
+    """tail: steps run the few-frames form (edge-parallel pass) whenever the
+    admitted-but-unharvested count allows; full: never (tail threshold 0)."""
     F = 48
     fams = [_family(m, k, N, e, F, seed=10 * i + 1) for i, (_, m, k, N, e) in enumerate(MIX)]
     codes = [D.Code.from_synth(f[0]) for f in fams]
+    if tail == "full":
+        for c in codes:
+            c.set_tuning(tail_frames=0)
     alone = []
     for code, (sc, enc, cw, llr) in zip(codes, fams):
         r = D.decode(code, torch.from_numpy(llr).cuda(), 30, prec=prec, mode="fused")
