@@ -167,6 +167,19 @@ int32_t ldpc_fd_decode_posterior(ldpc_fd_code code, int32_t frames, const float 
                                  const int32_t *iters, const void *workspace, int64_t workspace_bytes,
                                  double *posterior, void *stream);
 
+/* Soft output and symbol-MAP decisions after an ldpc_fd_decode in FUSED mode
+ * (same conditions as ldpc_fd_decode_posterior): symmap[frames][N] (device
+ * uint8) receives argmax_x p_v(x) at each frame's stopping round (the
+ * symbol-MAP decision, Sec. 3.1 Eq. (3), through the inverse transform of
+ * Eq. (4); ties go to the smaller symbol), and posterior (device
+ * float[frames][N][2^m], may be NULL) the normalised pmf, formed in FP64 as
+ * above and rounded to FP32.  symmap can differ from the decode's bitwise-MAP
+ * hard decisions where the posterior is not concentrated.
+ * Errors: as ldpc_fd_decode_posterior. */
+int32_t ldpc_fd_decode_symbols(ldpc_fd_code code, int32_t frames, const float *llr, int32_t prec,
+                               const int32_t *iters, const void *workspace, int64_t workspace_bytes,
+                               uint8_t *symmap, float *posterior, void *stream);
+
 /* ---- Decoding pool: continuous batching over several codes -------------------
  * A pool owns, for each of its codes, `slots[k]` frame slots in device memory
  * (message state, decisions and per-frame round counter; ldpc_fd_pool_slot_bytes
@@ -204,8 +217,11 @@ int32_t ldpc_fd_pool_submit(ldpc_fd_pool pool, int32_t code, const float *llr, i
                             const uint64_t *tags, int32_t max_iter, int32_t *admitted);
 
 /* Enqueue `passes` (1..1000) passes over the active frames of every code: one
- * replay of a captured graph whose per-code branches run concurrently.
- * Asynchronous.  Errors: E_INVALID, E_UNSUPPORTED, E_HIP. */
+ * replay of a captured graph whose per-code branches run concurrently.  A code
+ * whose admitted-but-unharvested frames number at most its tail threshold
+ * (LDPC_FD_TUNE_TAIL_FRAMES) runs the few-frames form in this step; steps are
+ * captured once per (passes, form per code) with the codes' tuning at that
+ * time.  Asynchronous.  Errors: E_INVALID, E_UNSUPPORTED, E_HIP. */
 int32_t ldpc_fd_pool_step(ldpc_fd_pool pool, int32_t passes);
 
 /* Collect up to cap stopped frames of code `code` (synchronises the pool's

@@ -38,6 +38,8 @@ _SIGS = {
     "ldpc_fd_posterior": (_i32, [_c_void_p, _i32, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "ldpc_fd_decode_posterior": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _c_void_p, _c_void_p, _i64, _c_void_p,
                                         _c_void_p]),
+    "ldpc_fd_decode_symbols": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _c_void_p, _c_void_p, _i64, _c_void_p,
+                                      _c_void_p, _c_void_p]),
     "ldpc_fd_set_tuning": (_i32, [_c_void_p, _i32, _i32]),
     "ldpc_fd_get_tuning": (_i32, [_c_void_p, _i32, ctypes.POINTER(_i32)]),
     "ldpc_fd_profile_enable": (_i32, [_i32]),
@@ -186,6 +188,20 @@ class Decoder:
         _check(lib().ldpc_fd_decode_posterior(self.code.handle, F, _ptr(llr), PREC[self.prec], _ptr(self.iters),
                                               _ptr(self.workspace), self.ws_bytes, _ptr(out), _stream()))
         return out
+
+    def symbols(self, soft: bool = False):
+        """Symbol-MAP decisions [F, N] (uint8) of the last decode's frames at their
+        stopping rounds, and with soft=True also their FP32 posteriors [F, N, q]
+        (FUSED mode; ldpc_fd_decode_symbols)."""
+        import torch
+        if self.mode != "fused":
+            raise ValueError("symbol decisions of a decode need the fused mode's message buffers")
+        llr, F = self._last
+        sym = torch.empty((F, self.code.N), dtype=torch.uint8, device=llr.device)
+        post = torch.empty((F, self.code.N, self.code.q), dtype=torch.float32, device=llr.device) if soft else None
+        _check(lib().ldpc_fd_decode_symbols(self.code.handle, F, _ptr(llr), PREC[self.prec], _ptr(self.iters),
+                                            _ptr(self.workspace), self.ws_bytes, _ptr(sym), _ptr(post), _stream()))
+        return (sym, post) if soft else sym
 
 
 def decode(code: Code, llr, max_iter: int, prec: str = "fp32", mode: str = "fused"):

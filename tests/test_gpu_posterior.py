@@ -98,3 +98,31 @@ def test_decode_posterior_at_stopping_round(case, prec):
     tol = {"fp32": 1e-4, "fp16": 1e-2}[prec]
     assert np.median(l1) < tol and l1.max() < 100 * tol
     gcode.close()
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[5], CASES[7]], ids=lambda c: c[0])
+def test_symbol_map_and_soft_output(case):
+    """Symbol-MAP decisions (argmax of the posterior, Sec. 3.1 Eq. (3)) and FP32
+    soft output at the stopping round: the soft output is the FP64 posterior
+    rounded, the decisions are the oracle's symbol-MAP decisions on the frames
+    that follow its trajectory, away from near-ties."""
+    name, m, k, N, F, ebn0 = case
+    print(f"[case] symbols {name} F={F}", flush=True)
+    code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0)
+    gcode = D.Code.from_synth(code)
+    L = _dev(llr)
+    dec = D.Decoder(gcode, F, "fp32", "fused")
+    r = dec(L, 20)
+    sym, soft = dec.symbols(soft=True)
+    post64 = dec.posterior().cpu().numpy()
+    sym, soft = sym.cpu().numpy(), soft.cpu().numpy()
+    assert np.array_equal(soft, post64.astype(np.float32))
+    assert np.array_equal(sym, post64.argmax(-1))
+    ref = odecode(tc, llr.astype(np.float64), 20)
+    same = (r["iters"].cpu().numpy() == ref.iters) & (r["hard"].cpu().numpy() == ref.hard).all(1)
+    top2 = np.sort(ref.post, axis=-1)[..., -2:]
+    clear = (top2[..., 1] - top2[..., 0]) > 1e-3          # symbols whose MAP is not a near-tie
+    sel = same[:, None] & clear
+    assert sel.sum() > 0.9 * same.sum() * N
+    assert np.array_equal(sym[sel], ref.symmap[sel])
+    gcode.close()
