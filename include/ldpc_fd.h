@@ -121,6 +121,21 @@ int32_t ldpc_fd_decode(ldpc_fd_code code, int32_t frames, const float *llr, int3
                        int32_t *iters, uint32_t *status, void *workspace,
                        int64_t workspace_bytes, void *stream);
 
+/* Decode from symbol priors instead of BPSK LLRs (Sec. 2.1: the channel input
+ * is Pr(X_v = x | Y_v = y_v) for every symbol, any memoryless channel).
+ * prior: device float [frames][N][2^m], entry x of row (f, v) proportional to
+ * Pr(X_v = x | y) (nonnegative, not all zero; rows need not be normalised).
+ * The variable node convolves with the prior through two Hadamard transforms
+ * (Y = WHT(p0 . WHT(X))) instead of the m butterflies of the BPSK form; FUSED
+ * mode only (the workspace of ldpc_fd_workspace_bytes(..., FUSED)); the
+ * PRECISE and DECISION_MFMA tuning keys do not apply.  Outputs, stopping rule
+ * and errors as ldpc_fd_decode (E_UNSUPPORTED is not returned).  The
+ * posterior and symbol entry points below take BPSK LLRs and do not apply to
+ * such decodes. */
+int32_t ldpc_fd_decode_prior(ldpc_fd_code code, int32_t frames, const float *prior, int32_t max_iter,
+                             int32_t prec, uint8_t *hard, uint8_t *synd, int32_t *iters, uint32_t *status,
+                             void *workspace, int64_t workspace_bytes, void *stream);
+
 /* One flooding round from an imported state, for message-level parity checks
  * (Sec. 3.2 VARIABLE TO CHECK, TENTATIVE DECISION, then CHECK TO VARIABLE):
  *   from c2v_in = Lambda_cv^(l) (FP32 message layout above; NULL means round 0,

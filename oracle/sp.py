@@ -230,19 +230,27 @@ class Result:
 
 
 def decode(code: TannerCode, llr: np.ndarray, max_iter: int, early_stop: bool = True,
-           chunk: int = 64) -> Result:
-    """Flooding SP decoding of every frame of llr [F, N, m] (Sec. 2, steps 1-4)."""
-    llr = np.asarray(llr, dtype=np.float64)
-    F = llr.shape[0]
-    parts = [_decode_chunk(code, llr[i:i + chunk], max_iter, early_stop) for i in range(0, F, chunk)]
+           chunk: int = 64, prior: np.ndarray | None = None) -> Result:
+    """Flooding SP decoding of every frame of llr [F, N, m] (Sec. 2, steps 1-4).
+    With prior [F, N, q] (llr ignored, may be None) the channel input is the
+    symbol prior Pr(X_v = x | y_v) itself (INITIALIZATION, Sec. 2.1),
+    normalised per symbol."""
+    if prior is not None:
+        src = np.asarray(prior, dtype=np.float64)
+        src = src / src.sum(axis=-1, keepdims=True)
+    else:
+        src = np.asarray(llr, dtype=np.float64)
+    F = src.shape[0]
+    parts = [_decode_chunk(code, src[i:i + chunk], max_iter, early_stop, prior is not None)
+             for i in range(0, F, chunk)]
     if not parts:
-        parts = [_decode_chunk(code, llr, max_iter, early_stop)]
+        parts = [_decode_chunk(code, src, max_iter, early_stop, prior is not None)]
     return Result(*[np.concatenate([getattr(p, f) for p in parts]) for f in Result.__dataclass_fields__])
 
 
-def _decode_chunk(code, llr, max_iter, early_stop):
-    F, N, M, q, m = llr.shape[0], code.N, code.M, code.q, code.m
-    p0 = channel_prior(llr, m)
+def _decode_chunk(code, src, max_iter, early_stop, is_prior=False):
+    F, N, M, q, m = src.shape[0], code.N, code.M, code.q, code.m
+    p0 = src if is_prior else channel_prior(src, m)
     res = Result(hard=np.zeros((F, N), np.int64), symmap=np.zeros((F, N), np.int64),
                  synd=np.zeros((F, M), np.int64), fsynd=np.zeros((F, M), np.int64),
                  iters=np.zeros(F, np.int64), converged=np.zeros(F, bool),

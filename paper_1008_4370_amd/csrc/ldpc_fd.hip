@@ -56,7 +56,7 @@ struct ldpc_fd_code_s {
   // Captured chunks of rounds of the fused decoder, keyed by everything their
   // kernel arguments depend on.
   struct GraphKey {
-    int F, prec, chunk, max_iter, logr, blocks, tail;
+    int F, prec, chunk, max_iter, logr, blocks, tail, ar;
     const void *ws, *llr, *hard, *synd, *iters, *status;
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
   };
@@ -132,39 +132,46 @@ struct Impl {
   }
   // Edge-parallel pass (k_fused_split) over at most Fmax active frames: one
   // workgroup of KMAX wavefronts per (frame group, check), grid-stride.
+  // ar: arithmetic form of the variable node (kFp32, kFp64, kSymbolPrior).
   template <typename S>
   static void fused_split(const DevCode& cd, int Fmax, const float* prior, S* buf0, S* buf1, uint8_t* hard,
                           uint8_t* fsw, const int* alist, const int* nact, const int* rnd, const int* maxit,
-                          int maxit_all, bool precise, hipStream_t s) {
+                          int maxit_all, int ar, hipStream_t s) {
     if (Fmax == 0) return;
     const long items = (long)((Fmax + G::T - 1) / G::T) * cd.M;
     const dim3 grid((unsigned)std::min<long>(items, 65536)), block(64 * KMAX);
     const size_t lds_bytes = (size_t)2 * KMAX * G::T * G::QP * sizeof(float);
-    if (precise)
-      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, true>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
+    if (ar == kFp64)
+      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kFp64>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
                          fsw, alist, nact, rnd, maxit, maxit_all);
+    else if (ar == kSymbolPrior)
+      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kSymbolPrior>), grid, block, lds_bytes, s, cd, prior, buf0, buf1,
+                         hard, fsw, alist, nact, rnd, maxit, maxit_all);
     else
-      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, false>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
+      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kFp32>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
                          fsw, alist, nact, rnd, maxit, maxit_all);
   }
   template <typename S>
   static void fused(const DevCode& cd, int Fmax, const float* prior, S* buf0, S* buf1, uint8_t* hard, uint8_t* fsw,
                     const int* alist, const int* nact, const int* rnd, const int* maxit, int maxit_all, int cap,
-                    bool precise, bool mfma, hipStream_t s) {
+                    int ar, bool mfma, hipStream_t s) {
     if (Fmax == 0) return;
     const dim3 grid(fused_blocks(cd, Fmax, cap)), block(64 * kWaves);
     if constexpr (kMfmaDecision<G>) {
-      if (mfma && !precise) {
-        hipLaunchKernelGGL((k_fused<G, KMAX, S, false, true>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
+      if (mfma && ar == kFp32) {
+        hipLaunchKernelGGL((k_fused<G, KMAX, S, kFp32, true>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
                            alist, nact, rnd, maxit, maxit_all);
         return;
       }
     }
-    if (precise)
-      hipLaunchKernelGGL((k_fused<G, KMAX, S, true, false>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
+    if (ar == kFp64)
+      hipLaunchKernelGGL((k_fused<G, KMAX, S, kFp64, false>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
                          alist, nact, rnd, maxit, maxit_all);
+    else if (ar == kSymbolPrior)
+      hipLaunchKernelGGL((k_fused<G, KMAX, S, kSymbolPrior, false>), grid, block, lds(), s, cd, prior, buf0, buf1,
+                         hard, fsw, alist, nact, rnd, maxit, maxit_all);
     else
-      hipLaunchKernelGGL((k_fused<G, KMAX, S, false, false>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
+      hipLaunchKernelGGL((k_fused<G, KMAX, S, kFp32, false>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
                          alist, nact, rnd, maxit, maxit_all);
   }
 };
@@ -486,13 +493,18 @@ int32_t ldpc_fd_workspace_bytes(ldpc_fd_code c, int32_t frames, int32_t prec, in
   return LDPC_FD_OK;
 }
 
-int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_iter, int32_t prec, int32_t mode,
-                       uint8_t* hard, uint8_t* synd, int32_t* iters, uint32_t* status, void* workspace,
-                       int64_t workspace_bytes, void* stream) {
+namespace {
+
+// Decode from BPSK LLRs (llr) or from symbol priors (prior, FUSED mode only).
+int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* prior, int32_t max_iter, int32_t prec,
+                    int32_t mode, uint8_t* hard, uint8_t* synd, int32_t* iters, uint32_t* status, void* workspace,
+                    int64_t workspace_bytes, void* stream) {
   if (!c) return fail(LDPC_FD_E_INVALID, "code is NULL");
   if (F < 0 || max_iter < 1) return fail(LDPC_FD_E_INVALID, "frames < 0 or max_iter < 1");
   if (F == 0) return LDPC_FD_OK;
-  if (!llr || !hard || !synd || !iters || !status || !workspace) return fail(LDPC_FD_E_INVALID, "NULL buffer");
+  if (!(llr || prior) || !hard || !synd || !iters || !status || !workspace)
+    return fail(LDPC_FD_E_INVALID, "NULL buffer");
+  if (prior && mode != LDPC_FD_MODE_FUSED) return fail(LDPC_FD_E_UNSUPPORTED, "symbol priors need the FUSED mode");
   int64_t need = 0;
   int32_t rc = ldpc_fd_workspace_bytes(c, F, prec, mode, &need);
   if (rc) return rc;
@@ -532,7 +544,14 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
   fused_layout(c, F, prec, (char*)workspace, &w);
   hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, (uint32_t*)nullptr, w.unsat, w.mism, w.alist,
                      w.nact, iters, status, w.rnd, 0);
-  launch_prior(c, F, llr, w.prior, s);
+  // the variable node's channel input: prior factors formed from the LLRs, or
+  // the caller's symbol priors read in place
+  const float* tp = w.prior;
+  if (prior)
+    tp = prior;
+  else
+    launch_prior(c, F, llr, w.prior, s);
+  const int ar = prior ? kSymbolPrior : c->precise ? kFp64 : kFp32;
   // One pass over the active frames (each at its own round, see k_fused),
   // syndromes of the decisions it formed, stopping rule and compaction.
   auto enqueue_round = [&](hipStream_t st, hipEvent_t e0, hipEvent_t e1, int lr, bool tail) {
@@ -543,11 +562,11 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
       auto run = [&](auto* b0, auto* b1) {
         using S = std::remove_pointer_t<decltype(b0)>;
         if (tail && c->split)
-          I::template fused_split<S>(cd, std::min(F, std::max(c->tail_frames, 1)), w.prior, b0, b1, hard, w.fsw,
-                                     w.alist, w.nact, w.rnd, nullptr, max_iter, c->precise, st);
+          I::template fused_split<S>(cd, std::min(F, std::max(c->tail_frames, 1)), tp, b0, b1, hard, w.fsw,
+                                     w.alist, w.nact, w.rnd, nullptr, max_iter, ar, st);
         else
-          I::template fused<S>(cd, F, w.prior, b0, b1, hard, w.fsw, w.alist, w.nact, w.rnd, nullptr, max_iter,
-                               c->blocks, c->precise, c->mfma, st);
+          I::template fused<S>(cd, F, tp, b0, b1, hard, w.fsw, w.alist, w.nact, w.rnd, nullptr, max_iter,
+                               c->blocks, ar, c->mfma, st);
       };
       if (prec == LDPC_FD_FP32)
         run((float*)w.buf[0], (float*)w.buf[1]);
@@ -606,8 +625,9 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
     key.logr = lr;
     key.blocks = c->blocks;
     key.tail = tail ? 1 : 0;
+    key.ar = ar;
     key.ws = workspace;
-    key.llr = llr;
+    key.llr = tp;
     key.hard = hard;
     key.synd = synd;
     key.iters = iters;
@@ -646,6 +666,24 @@ int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_
   }
   HIP_TRY(hipGetLastError());
   return LDPC_FD_OK;
+}
+
+}  // namespace
+
+int32_t ldpc_fd_decode(ldpc_fd_code c, int32_t F, const float* llr, int32_t max_iter, int32_t prec, int32_t mode,
+                       uint8_t* hard, uint8_t* synd, int32_t* iters, uint32_t* status, void* workspace,
+                       int64_t workspace_bytes, void* stream) {
+  if (F > 0 && !llr) return fail(LDPC_FD_E_INVALID, "NULL buffer");
+  return decode_impl(c, F, llr, nullptr, max_iter, prec, mode, hard, synd, iters, status, workspace,
+                     workspace_bytes, stream);
+}
+
+int32_t ldpc_fd_decode_prior(ldpc_fd_code c, int32_t F, const float* prior, int32_t max_iter, int32_t prec,
+                             uint8_t* hard, uint8_t* synd, int32_t* iters, uint32_t* status, void* workspace,
+                             int64_t workspace_bytes, void* stream) {
+  if (F > 0 && !prior) return fail(LDPC_FD_E_INVALID, "NULL buffer");
+  return decode_impl(c, F, nullptr, prior, max_iter, prec, LDPC_FD_MODE_FUSED, hard, synd, iters, status,
+                     workspace, workspace_bytes, stream);
 }
 
 int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* c2v_in, float* v2c_out,
@@ -704,9 +742,9 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
           if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, in, n_msg / 4);
         }
         if (c2v_in)
-          I::template fused<S>(cd, F, prior, out, in, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise, c->mfma, s);
+          I::template fused<S>(cd, F, prior, out, in, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise ? kFp64 : kFp32, c->mfma, s);
         else
-          I::template fused<S>(cd, F, prior, nullptr, out, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise, c->mfma, s);
+          I::template fused<S>(cd, F, prior, nullptr, out, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise ? kFp64 : kFp32, c->mfma, s);
         if (prec != LDPC_FD_FP32)
           hipLaunchKernelGGL((k_convert<S, float>), dim3(g), dim3(256), 0, s, (const S*)out, c2v_out, n_msg / 4);
       };

@@ -375,25 +375,50 @@ struct EdgeLoads {
   float x[G::R];
   float o[G::R];
   float l[G::LOGQ];   // prior factors t_i = tanh(L_i / 2) of the variable
+  float pr[G::R];     // symbol prior p_v^(0)(x) (arithmetic form kSymbolPrior)
 };
 
-template <class G, typename S>
+// Arithmetic forms of the variable node: BPSK prior factors in FP32 or FP64,
+// or a symbol prior pmf per variable (FP32).
+constexpr int kFp32 = 0, kFp64 = 1, kSymbolPrior = 2;
+
+template <class G, typename S, int AR>
 __device__ __forceinline__ void issue_edge(const DevCode& cd, const float* __restrict__ tp, const S* __restrict__ cin,
                                            size_t fb, int f, int e, const FrameState& fs, bool any_decide, int zl,
                                            EdgeLoads<G, S>& L) {
   const int v = uni(cd.e_var[e]);
   const int eo = uni(cd.e_other[e]);
-  const float* lp = tp + ((size_t)f * cd.N + v) * G::LOGQ;
+  if constexpr (AR == kSymbolPrior) {
+    load_msg<G, float>(tp + ((size_t)f * cd.N + v) * G::Q, zl, L.pr);
+  } else {
+    const float* lp = tp + ((size_t)f * cd.N + v) * G::LOGQ;
 #pragma unroll
-  for (int i = 0; i < G::LOGQ; ++i) L.l[i] = lp[i];
+    for (int i = 0; i < G::LOGQ; ++i) L.l[i] = lp[i];
+  }
   if (!fs.first) load_msg<G, S>(cin + fb + (size_t)eo * G::Q, zl, L.x);
   if (any_decide && e < eo && fs.decide) load_msg<G, S>(cin + fb + (size_t)e * G::Q, zl, L.o);
+}
+
+// XOR convolution with a general symbol prior (Sec. 2.1: the channel gives
+// Pr(X_v = x | y_v) directly): Y = P0 (*) X is the transform of p0 . x, where x
+// is the inverse transform of X, so Y = WHT(p0 . WHT(X)) up to a positive
+// factor.  wht_s returns s(z) times the transform, s(z) = (-1)^popcount(zl)
+// constant per lane; multiplying by s after each transform removes it.
+template <class G>
+__device__ __forceinline__ void conv_symbol_prior(float (&v)[G::R], const float (&pr)[G::R], int zl) {
+  const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
+  wht_s<G>(v, zl);
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) v[r] *= sz * pr[r];
+  wht_s<G>(v, zl);
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) v[r] *= sz;
 }
 
 // P (precise): the variable node in FP64 (prior factors given as signed
 // complements, see conv_prior_d).
 // DM: the decision's transforms on the matrix cores (decide_mfma).
-template <class G, int KMAX, typename S, bool P, bool DM>
+template <class G, int KMAX, typename S, int AR, bool DM>
 __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __restrict__ tp, S* __restrict__ buf0,
                                            S* __restrict__ buf1, uint8_t* __restrict__ hard,
                                            uint8_t* __restrict__ fsw, int f, bool valid, const FrameState& fs,
@@ -407,19 +432,20 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
   float st[KMAX][G::R];   // Lambda~_vc of each edge (check coordinates)
   // sum of magnitudes over the check's edges (P: FP64, so that a small
   // extrinsic sum next to a large own term survives total minus own)
+  constexpr bool P = AR == kFp64;
   using Acc = typename std::conditional<P, double, float>::type;
   Acc smag[G::R];
 #pragma unroll
   for (int r = 0; r < G::R; ++r) smag[r] = 0;
   // edge j+1's loads are in flight while edge j is computed
   EdgeLoads<G, S> nxt;
-  issue_edge<G, S>(cd, tp, cin, fb, f, e0, fs, any_decide, zl, nxt);
+  issue_edge<G, S, AR>(cd, tp, cin, fb, f, e0, fs, any_decide, zl, nxt);
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j < deg) {
       const int e = e0 + j;
       const EdgeLoads<G, S> cur = nxt;
-      if (j + 1 < deg) issue_edge<G, S>(cd, tp, cin, fb, f, e + 1, fs, any_decide, zl, nxt);
+      if (j + 1 < deg) issue_edge<G, S, AR>(cd, tp, cin, fb, f, e + 1, fs, any_decide, zl, nxt);
       const int v = uni(cd.e_var[e]);
       const int eo = uni(cd.e_other[e]);
       const int h = uni(cd.e_label[e]);
@@ -437,7 +463,10 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
 #pragma unroll
         for (int r = 0; r < G::R; ++r)
           st[j][r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
-        conv_prior<G>(st[j], t);
+        if constexpr (AR == kSymbolPrior)
+          conv_symbol_prior<G>(st[j], cur.pr, zl);
+        else
+          conv_prior<G>(st[j], t);
       }
       if (any_decide && e < eo) {
         float xo[G::R];
@@ -501,7 +530,7 @@ constexpr int kXcds = 8;
 // from the same XCD's L2.  gridDim.x must be a multiple of 8.
 // At least 2 wavefronts per SIMD (<= 256 VGPRs): the stash of a check's
 // messages is the largest register consumer.
-template <class G, int KMAX, typename S, bool P, bool DM>
+template <class G, int KMAX, typename S, int AR, bool DM>
 __global__ __launch_bounds__(256, 2) void k_fused(DevCode cd, const float* __restrict__ tp, S* __restrict__ buf0,
                                                S* __restrict__ buf1, uint8_t* __restrict__ hard,
                                                uint8_t* __restrict__ fsw, const int* __restrict__ alist,
@@ -525,7 +554,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(DevCode cd, const float* __res
     const bool valid = slot < nact;
     const int f = alist[valid ? slot : nact - 1];
     const FrameState fs = frame_state(rnd, maxit, maxit_all, f);
-    fused_item<G, KMAX, S, P, DM>(cd, tp, buf0, buf1, hard, fsw, f, valid, fs, c, lds, rb, cf, zl);
+    fused_item<G, KMAX, S, AR, DM>(cd, tp, buf0, buf1, hard, fsw, f, valid, fs, c, lds, rb, cf, zl);
   }
 }
 
@@ -537,7 +566,7 @@ __global__ __launch_bounds__(256, 2) void k_fused(DevCode cd, const float* __res
 // results are bit-identical to k_fused) and forms its own extrinsic output.
 // A check's latency is then one edge instead of k.  LDS: per wavefront T rows
 // of Q floats for the label permutations, and the stash [KMAX][T][Q].
-template <class G, int KMAX, typename S, bool P>
+template <class G, int KMAX, typename S, int AR>
 __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const float* __restrict__ tp,
                                                            S* __restrict__ buf0, S* __restrict__ buf1,
                                                            uint8_t* __restrict__ hard, uint8_t* __restrict__ fsw,
@@ -553,6 +582,7 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
   const long items = (long)groups * cd.M;
   const int fl = lane / G::L, zl = lane % G::L;
   const int rb = (j * G::T + fl) * G::QP, cf = G::swz(fl);
+  constexpr bool P = AR == kFp64;
   using Acc = typename std::conditional<P, double, float>::type;
   for (long it = blockIdx.x; it < items; it += gridDim.x) {
     const int g = (int)(it / cd.M), c = (int)(it % cd.M);
@@ -570,7 +600,7 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
     if (j < deg) {
       const int e = e0 + j;
       EdgeLoads<G, S> cur;
-      issue_edge<G, S>(cd, tp, cin, fb, f, e, fs, any_decide, zl, cur);
+      issue_edge<G, S, AR>(cd, tp, cin, fb, f, e, fs, any_decide, zl, cur);
       const int v = uni(cd.e_var[e]);
       const int eo = uni(cd.e_other[e]);
       const int h = uni(cd.e_label[e]);
@@ -587,7 +617,10 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
       } else {
 #pragma unroll
         for (int r = 0; r < G::R; ++r) st[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
-        conv_prior<G>(st, t);
+        if constexpr (AR == kSymbolPrior)
+          conv_symbol_prior<G>(st, cur.pr, zl);
+        else
+          conv_prior<G>(st, t);
       }
       if (any_decide && e < eo) {
         float xo[G::R];

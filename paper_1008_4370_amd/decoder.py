@@ -40,6 +40,8 @@ _SIGS = {
                                         _c_void_p]),
     "ldpc_fd_decode_symbols": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _c_void_p, _c_void_p, _i64, _c_void_p,
                                       _c_void_p, _c_void_p]),
+    "ldpc_fd_decode_prior": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _i32, _c_void_p, _c_void_p, _c_void_p,
+                                    _c_void_p, _c_void_p, _i64, _c_void_p]),
     "ldpc_fd_set_tuning": (_i32, [_c_void_p, _i32, _i32]),
     "ldpc_fd_get_tuning": (_i32, [_c_void_p, _i32, ctypes.POINTER(_i32)]),
     "ldpc_fd_profile_enable": (_i32, [_i32]),
@@ -177,12 +179,26 @@ class Decoder:
         self._last = (llr, F)
         return dict(hard=self.hard[:F], synd=self.synd[:F], iters=self.iters[:F], status=self.status[:F])
 
+    def decode_prior(self, prior, max_iter: int):
+        """prior: device float32 [F, N, q] symbol priors (ldpc_fd_decode_prior;
+        FUSED mode).  Returns views of the outputs."""
+        F = prior.shape[0]
+        assert self.mode == "fused" and F <= self.frames and prior.is_contiguous() and prior.dtype.itemsize == 4
+        assert tuple(prior.shape[1:]) == (self.code.N, self.code.q)
+        _check(lib().ldpc_fd_decode_prior(self.code.handle, F, _ptr(prior), int(max_iter), PREC[self.prec],
+                                          _ptr(self.hard), _ptr(self.synd), _ptr(self.iters), _ptr(self.status),
+                                          _ptr(self.workspace), self.ws_bytes, _stream()))
+        self._last = None
+        return dict(hard=self.hard[:F], synd=self.synd[:F], iters=self.iters[:F], status=self.status[:F])
+
     def posterior(self):
         """Validation mode: FP64 posteriors [F, N, q] of the last decode's frames
         at their stopping rounds (FUSED mode; ldpc_fd_decode_posterior)."""
         import torch
         if self.mode != "fused":
             raise ValueError("posteriors of a decode need the fused mode's message buffers")
+        if not self._last:
+            raise ValueError("posteriors follow a decode from BPSK LLRs")
         llr, F = self._last
         out = torch.empty((F, self.code.N, self.code.q), dtype=torch.float64, device=llr.device)
         _check(lib().ldpc_fd_decode_posterior(self.code.handle, F, _ptr(llr), PREC[self.prec], _ptr(self.iters),
@@ -196,6 +212,8 @@ class Decoder:
         import torch
         if self.mode != "fused":
             raise ValueError("symbol decisions of a decode need the fused mode's message buffers")
+        if not self._last:
+            raise ValueError("symbol decisions follow a decode from BPSK LLRs")
         llr, F = self._last
         sym = torch.empty((F, self.code.N), dtype=torch.uint8, device=llr.device)
         post = torch.empty((F, self.code.N, self.code.q), dtype=torch.float32, device=llr.device) if soft else None

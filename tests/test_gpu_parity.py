@@ -390,3 +390,43 @@ def test_edge_parallel_tail_pass_is_identical(case, precise):
         for key in ("hard", "synd", "iters", "status"):
             assert np.array_equal(a[key], b[key]), key
     gcode.close()
+
+
+def _qsc_prior(cw, q, eps, seed):
+    """q-ary symmetric channel: the received symbol is the sent one with
+    probability 1 - eps, else uniform over the others; prior of each symbol."""
+    rng = np.random.default_rng(seed)
+    F, N = cw.shape
+    flip = rng.random((F, N)) < eps
+    other = (cw + rng.integers(1, q, size=(F, N))) % q
+    rx = np.where(flip, other, cw)
+    p0 = np.full((F, N, q), eps / (q - 1), dtype=np.float32)
+    np.put_along_axis(p0, rx[..., None], np.float32(1.0 - eps), axis=2)
+    return p0
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[5], CASES[8]], ids=lambda c: c[0])
+def test_symbol_prior_decoding(case):
+    """Decoding from symbol priors (ldpc_fd_decode_prior): with the BPSK prior it
+    follows the LLR decode (>= 95% of frames identical), and on a q-ary
+    symmetric channel it matches the oracle run on the same priors."""
+    name, m, k, N, F, ebn0 = case
+    print(f"[case] symbol prior {name} F={F}", flush=True)
+    code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0)
+    gcode = D.Code.from_synth(code)
+    dec = D.Decoder(gcode, F, "fp32", "fused")
+    a = {k2: v.cpu().numpy().copy() for k2, v in dec(_dev(llr), 30).items()}
+    p0 = channel_prior(llr.astype(np.float64), m).astype(np.float32)
+    b = {k2: v.cpu().numpy().copy() for k2, v in dec.decode_prior(_dev(p0), 30).items()}
+    same = (a["iters"] == b["iters"]) & (a["hard"] == b["hard"]).all(1)
+    assert same.mean() >= 0.95   # FP32 trajectories of the two arithmetic routes may part
+    assert np.array_equal(b["synd"].astype(np.int64), enc.syndrome(b["hard"].astype(np.int64)))
+    eps = 0.08
+    pq = _qsc_prior(cw, tc.q, eps, seed=17)
+    g = {k2: v.cpu().numpy().copy() for k2, v in dec.decode_prior(_dev(pq), 30).items()}
+    ref = odecode(tc, None, 30, prior=pq.astype(np.float64))
+    same = (g["iters"] == ref.iters) & (g["hard"] == ref.hard).all(1)
+    print(f"  BPSK prior vs LLR identical {np.mean((a['iters'] == b['iters']) & (a['hard'] == b['hard']).all(1)):.3f};"
+          f" q-SC vs oracle identical {same.mean():.3f}, oracle FER {np.mean((ref.hard != cw).any(1)):.3f}", flush=True)
+    assert same.mean() >= 0.95
+    gcode.close()

@@ -245,3 +245,39 @@ def test_table1_operation_counts():
     assert lf.counts["var_CONV"] == 2 * code.N
     assert lf.counts["tent_CONV"] == 2 * code.N
     assert lf.counts["check_ADD"] == int(np.sum(deg * (deg - 2)))
+
+
+@pytest.mark.parametrize("m,nchk,seed", [(2, 3, 11), (3, 3, 12), (2, 4, 13)])
+def test_symbol_prior_input_tree_marginals(m, nchk, seed):
+    """Channel input given as symbol priors Pr(X_v = x | y_v) (Sec. 2.1) that do
+    not factor over bits: on a cycle-free graph the posteriors are the exact
+    marginals of prod_v p0_v(x_v) over the codewords."""
+    code = synth.make_tree_code(nchk, m, seed)
+    enc = synth.Encoder(code)
+    q = 1 << m
+    rng = np.random.default_rng(200 + seed)
+    F = 2
+    p0 = rng.random((F, code.N, q)) ** 3 + 1e-3          # arbitrary positive, unnormalised
+    infos = np.array(list(itertools.product(range(q), repeat=enc.K)))
+    cws = enc.encode(infos)
+    tc = _tc(code)
+    res = decode(tc, None, 2 * nchk + 2, early_stop=False, prior=p0)
+    pn = p0 / p0.sum(-1, keepdims=True)
+    for f in range(F):
+        w = np.prod(pn[f, np.arange(code.N)[None, :], cws], axis=1)
+        for v in range(code.N):
+            marg = np.bincount(cws[:, v], weights=w, minlength=q)
+            assert np.allclose(res.post[f, v], marg / marg.sum(), atol=1e-12), (f, v)
+
+
+def test_symbol_prior_input_equals_llr_input():
+    """The BPSK prior passed as symbol priors decodes exactly like the LLRs."""
+    code = synth.make_code(40, 4, 3, seed_graph=31, seed_labels=32)
+    tc = _tc(code)
+    enc = synth.Encoder(code)
+    cw = synth.random_codewords(enc, 6, seed=33)
+    llr = synth.bpsk_awgn_llr(cw, 3, 2.0, code.design_rate, seed=34).astype(np.float64)
+    a = decode(tc, llr, 30)
+    b = decode(tc, None, 30, prior=channel_prior(llr, 3))
+    assert np.array_equal(a.hard, b.hard) and np.array_equal(a.iters, b.iters)
+    assert np.allclose(a.post, b.post, atol=1e-12)
