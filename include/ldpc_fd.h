@@ -127,9 +127,10 @@ int32_t ldpc_fd_decode(ldpc_fd_code code, int32_t frames, const float *llr, int3
  * Pr(X_v = x | y) (nonnegative, not all zero; rows need not be normalised).
  * The variable node convolves with the prior through two Hadamard transforms
  * (Y = WHT(p0 . WHT(X))) instead of the m butterflies of the BPSK form; FUSED
- * mode only (the workspace of ldpc_fd_workspace_bytes(..., FUSED)); the
- * PRECISE and DECISION_MFMA tuning keys do not apply.  Outputs, stopping rule
- * and errors as ldpc_fd_decode (E_UNSUPPORTED is not returned).  The
+ * mode and FP32 storage only (the workspace of ldpc_fd_workspace_bytes(...,
+ * FP32, FUSED)); the PRECISE and DECISION_MFMA tuning keys do not apply.
+ * Outputs, stopping rule and errors as ldpc_fd_decode; E_UNSUPPORTED for
+ * prec != FP32.  The
  * posterior and symbol entry points below take BPSK LLRs and do not apply to
  * such decodes. */
 int32_t ldpc_fd_decode_prior(ldpc_fd_code code, int32_t frames, const float *prior, int32_t max_iter,
@@ -274,7 +275,8 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *     precision; 0 (default) = FP32.  Unlike the other keys this one changes
  *     results: FP32 loses the small differences from certainty that decide
  *     messages where the channel and the check messages disagree.  A pool uses
- *     the setting its codes had when it was created.
+ *     the setting its codes had when it was created.  Not built for BF16
+ *     storage (decode, round and pool creation return E_UNSUPPORTED).
  *   LDPC_FD_TUNE_DECISION_MFMA: 1 = the three Hadamard transforms of the
  *     tentative decision run as FP16 MFMAs with FP32 accumulation (each FP32
  *     operand split into two FP16 terms, ~22 bits), in the variants with 4

@@ -141,13 +141,22 @@ struct Impl {
     const long items = (long)((Fmax + G::T - 1) / G::T) * cd.M;
     const dim3 grid((unsigned)std::min<long>(items, 65536)), block(64 * KMAX);
     const size_t lds_bytes = (size_t)2 * KMAX * G::T * G::QP * sizeof(float);
-    if (ar == kFp64)
-      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kFp64>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
-                         fsw, alist, nact, rnd, maxit, maxit_all);
-    else if (ar == kSymbolPrior)
-      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kSymbolPrior>), grid, block, lds_bytes, s, cd, prior, buf0, buf1,
-                         hard, fsw, alist, nact, rnd, maxit, maxit_all);
-    else
+    // built forms: FP64 variable node with FP32/FP16 storage, symbol priors with
+    // FP32 storage (the entry points reject the other combinations)
+    if constexpr (!std::is_same_v<S, bf16_t>) {
+      if (ar == kFp64) {
+        hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kFp64>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
+                           fsw, alist, nact, rnd, maxit, maxit_all);
+        return;
+      }
+    }
+    if constexpr (std::is_same_v<S, float>) {
+      if (ar == kSymbolPrior) {
+        hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kSymbolPrior>), grid, block, lds_bytes, s, cd, prior, buf0,
+                           buf1, hard, fsw, alist, nact, rnd, maxit, maxit_all);
+        return;
+      }
+    }
       hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kFp32>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
                          fsw, alist, nact, rnd, maxit, maxit_all);
   }
@@ -164,13 +173,20 @@ struct Impl {
         return;
       }
     }
-    if (ar == kFp64)
-      hipLaunchKernelGGL((k_fused<G, KMAX, S, kFp64, false>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
-                         alist, nact, rnd, maxit, maxit_all);
-    else if (ar == kSymbolPrior)
-      hipLaunchKernelGGL((k_fused<G, KMAX, S, kSymbolPrior, false>), grid, block, lds(), s, cd, prior, buf0, buf1,
-                         hard, fsw, alist, nact, rnd, maxit, maxit_all);
-    else
+    if constexpr (!std::is_same_v<S, bf16_t>) {
+      if (ar == kFp64) {
+        hipLaunchKernelGGL((k_fused<G, KMAX, S, kFp64, false>), grid, block, lds(), s, cd, prior, buf0, buf1, hard,
+                           fsw, alist, nact, rnd, maxit, maxit_all);
+        return;
+      }
+    }
+    if constexpr (std::is_same_v<S, float>) {
+      if (ar == kSymbolPrior) {
+        hipLaunchKernelGGL((k_fused<G, KMAX, S, kSymbolPrior, false>), grid, block, lds(), s, cd, prior, buf0, buf1,
+                           hard, fsw, alist, nact, rnd, maxit, maxit_all);
+        return;
+      }
+    }
       hipLaunchKernelGGL((k_fused<G, KMAX, S, kFp32, false>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
                          alist, nact, rnd, maxit, maxit_all);
   }
@@ -505,6 +521,9 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   if (!(llr || prior) || !hard || !synd || !iters || !status || !workspace)
     return fail(LDPC_FD_E_INVALID, "NULL buffer");
   if (prior && mode != LDPC_FD_MODE_FUSED) return fail(LDPC_FD_E_UNSUPPORTED, "symbol priors need the FUSED mode");
+  if (prior && prec != LDPC_FD_FP32) return fail(LDPC_FD_E_UNSUPPORTED, "symbol priors need FP32 storage");
+  if (!prior && c->precise && prec == LDPC_FD_BF16 && mode == LDPC_FD_MODE_FUSED)
+    return fail(LDPC_FD_E_UNSUPPORTED, "the FP64 variable node needs FP32 or FP16 storage");
   int64_t need = 0;
   int32_t rc = ldpc_fd_workspace_bytes(c, F, prec, mode, &need);
   if (rc) return rc;
@@ -696,6 +715,8 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   if (c2v_in && (!hard || !fsynd || !synd)) return fail(LDPC_FD_E_INVALID, "decision outputs required");
   if (mode == LDPC_FD_MODE_PLAIN && !v2c_out) return fail(LDPC_FD_E_INVALID, "PLAIN round needs v2c_out");
   if (mode == LDPC_FD_MODE_FUSED && v2c_out) return fail(LDPC_FD_E_INVALID, "FUSED round does not form v2c_out");
+  if (mode == LDPC_FD_MODE_FUSED && c->precise && prec == LDPC_FD_BF16)
+    return fail(LDPC_FD_E_UNSUPPORTED, "the FP64 variable node needs FP32 or FP16 storage");
   if (mode != LDPC_FD_MODE_PLAIN && mode != LDPC_FD_MODE_FUSED) return fail(LDPC_FD_E_INVALID, "unknown mode");
   if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
   if (mode == LDPC_FD_MODE_PLAIN && prec != LDPC_FD_FP32) return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN is FP32 only");

@@ -430,3 +430,21 @@ def test_symbol_prior_decoding(case):
           f" q-SC vs oracle identical {same.mean():.3f}, oracle FER {np.mean((ref.hard != cw).any(1)):.3f}", flush=True)
     assert same.mean() >= 0.95
     gcode.close()
+
+
+def test_unbuilt_combinations_are_rejected():
+    """The FP64 variable node with BF16 storage and symbol priors with 16-bit
+    storage are not built: the entry points return E_UNSUPPORTED."""
+    code, enc, cw, llr, tc = _setup(6, 6, 60, 4, 2.5)
+    gcode = D.Code.from_synth(code)
+    gcode.set_tuning(precise=1)
+    with pytest.raises(D.LdpcFdError) as ei:
+        D.decode(gcode, _dev(llr), 10, prec="bf16", mode="fused")
+    assert ei.value.rc == -2
+    gcode.set_tuning(precise=0)
+    dec = D.Decoder(gcode, 4, "fp16", "fused")
+    p0 = channel_prior(llr.astype(np.float64), 6).astype(np.float32)
+    with pytest.raises(D.LdpcFdError) as ei:
+        dec.decode_prior(_dev(p0), 10)
+    assert ei.value.rc == -2
+    gcode.close()
