@@ -218,6 +218,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--precise", action="store_true",
                     help="time the FP64 variable node (tuning key PRECISE) as the headline")
+    ap.add_argument("--no-logsp-variant", action="store_true",
+                    help="skip timing the conventional log-domain SP decoder on the same batch")
     ap.add_argument("--no-precise-variant", action="store_true",
                     help="skip the extra timing of the FP64 variable node")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -311,6 +313,37 @@ def main():
         code.set_tuning(**before)
         del pdec
 
+    logsp_line = None
+    if args.mode == "fused" and args.prec == "fp32" and not args.no_logsp_variant:
+        # The same batch through the conventional log-domain SP decoder (the
+        # comparison of Table 1): whole-decode time, and the time of its check
+        # and variable kernels per frame-round next to the fused pass's.
+        ldec = D.Decoder(code, F, "fp32", "logsp")
+        ldec(llr, args.max_iter)
+        torch.cuda.synchronize()
+        D.profile_read(D.K_CHECK), D.profile_read(D.K_VAR)
+        D.profile_enable(not args.no_kernel_timing)
+        tl0 = time.perf_counter()
+        for _ in range(args.steps):
+            lout = ldec(llr, args.max_iter)
+        torch.cuda.synchronize()
+        lms = (time.perf_counter() - tl0) / args.steps * 1e3
+        D.profile_enable(False)
+        ck, _ = D.profile_read(D.K_CHECK)
+        vk, _ = D.profile_read(D.K_VAR)
+        lhard = lout["hard"].cpu().numpy()
+        lrounds = int(lout["iters"].sum())
+        logsp_line = {"ms_per_step": round(lms, 4),
+                      "value": round(F * batch.info_bits_per_frame / (lms / 1e3) / 1e6, 3),
+                      "fer": float(np.any(lhard != batch.cw, axis=1).mean()),
+                      "mean_iters": float(lout["iters"].float().mean()),
+                      "check_kernel_ms_per_step": round(ck / args.steps, 4),
+                      "var_kernel_ms_per_step": round(vk / args.steps, 4),
+                      "ns_per_frame_round": round((ck + vk) / args.steps * 1e6 / max(lrounds, 1), 2),
+                      "lfsp_ns_per_frame_round": round(kms / args.steps * 1e6 / max(int(out["iters"].sum()), 1), 2),
+                      "lfsp_speedup": round(lms / ms_step, 3)}
+        del ldec
+
     serve = None
     if args.serve_load > 0:
         # Continuous batching of the same frames arriving as a Poisson process
@@ -397,6 +430,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "precise_variant": precise_line,
+        "logsp_variant": logsp_line,
         "fer": float(frame_err.mean()),
         "ber": bit_err / (F * batch.code.N * batch.code.m),
         "mean_iters": float(iters.mean()),

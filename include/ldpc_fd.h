@@ -55,15 +55,24 @@ enum {
 /* Storage type of the message state (arithmetic is FP32 in every case). */
 enum { LDPC_FD_FP32 = 0, LDPC_FD_FP16 = 1, LDPC_FD_BF16 = 2 };
 
-/* Decoder variants (identical results up to rounding order):
+/* Decoder variants (PLAIN and FUSED: identical results up to rounding order):
  *  PLAIN: one kernel per node type per round, flooding schedule of Sec. 2
  *         (check-to-variable, variable-to-check, tentative decision), all frames
  *         processed until the host sees every frame stopped.
  *  FUSED: one pass per round over the checks; each pass recomputes the
  *         variable-to-check messages from the stored check-to-variable state,
  *         forms the tentative decision of the previous round, compacts the list
- *         of still-active frames on the device and runs in chunks of rounds. */
-enum { LDPC_FD_MODE_PLAIN = 0, LDPC_FD_MODE_FUSED = 1 };
+ *         of still-active frames on the device and runs in chunks of rounds.
+ *  LOGSP: the conventional log-domain sum-product decoder of Sec. 2.2, the
+ *         comparison point of Table 1: messages are log2 pmfs (FP32, maximum
+ *         normalised to 0, floored at -200), the check node forms each outgoing
+ *         message as the XOR convolution of the other k-1 incoming ones in the
+ *         log domain (forward/backward partial convolutions, 3(k-2) pairwise
+ *         convolutions of q^2 log-sum-exp terms), the variable node adds log
+ *         vectors; flooding schedule and stopping rule as PLAIN.  Same outputs
+ *         as the Log-Fourier modes up to rounding; FP32 storage only; the
+ *         PRECISE and DECISION_MFMA tuning keys do not apply. */
+enum { LDPC_FD_MODE_PLAIN = 0, LDPC_FD_MODE_FUSED = 1, LDPC_FD_MODE_LOGSP = 2 };
 
 /* status[f] bits */
 #define LDPC_FD_STATUS_CONVERGED 1u /* stopped on a passed codeword test */
@@ -148,12 +157,14 @@ int32_t ldpc_fd_decode_prior(ldpc_fd_code code, int32_t frames, const float *pri
  *   tentative decision of round l: hard[frames][N], fsynd[frames][M] (Fourier
  *   syndrome words, bit i = syndrome bit i+1 of the check) and synd[frames][M]
  *   (direct syndrome of hard).  All arrays are device memory in the FP32 message
- *   layout.  mode selects which kernels compute it (PLAIN or FUSED).  prec
+ *   layout.  mode selects which kernels compute it (PLAIN or FUSED; LOGSP
+ *   instead takes and writes log2 pmfs [frames][E][2^m] with maximum 0 in
+ *   c2v_in, v2c_out and c2v_out, v2c_out required).  prec
  *   selects the storage type the FUSED pass reads and writes: the imported
  *   state is rounded to it first and the result widened back to FP32, so the
  *   difference to an FP32 round is the one-round storage error (PLAIN: FP32
  *   only).  The call allocates temporary device memory and synchronises.
- * Errors: E_INVALID, E_UNSUPPORTED (PLAIN with prec != FP32), E_HIP. */
+ * Errors: E_INVALID, E_UNSUPPORTED (PLAIN or LOGSP with prec != FP32), E_HIP. */
 int32_t ldpc_fd_round(ldpc_fd_code code, int32_t frames, const float *llr, const float *c2v_in,
                       float *v2c_out, float *c2v_out, uint8_t *hard, uint8_t *fsynd,
                       uint8_t *synd, int32_t mode, int32_t prec, void *stream);

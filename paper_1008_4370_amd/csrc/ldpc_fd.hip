@@ -12,6 +12,7 @@
 
 #include "ldpc_fd.h"
 #include "lfsp_kernels.h"
+#include "logsp_kernels.h"
 
 using namespace ldpcfd;
 
@@ -217,6 +218,44 @@ bool dispatch_q(int kmax, int logr, Fn&& fn) {
   return false;
 }
 
+// Conventional log-domain SP kernels (LDPC_FD_MODE_LOGSP): one wavefront per
+// (frame, node), grid-stride over at most kLsBlocks workgroups.
+constexpr long kLsBlocks = 16384;
+
+template <int LOGQ>
+struct LogSp {
+  static unsigned grid(long items) { return (unsigned)std::max<long>(1, std::min(items, kLsBlocks)); }
+  // nf frames: alist[0..nf) (frames 0..nf-1 when alist is NULL)
+  static void check(const DevCode& cd, int nf, const int* alist, int kmax, const float* v2c, float* c2v,
+                    hipStream_t s) {
+    const long items = (long)nf * cd.M;
+    if (items == 0) return;
+    const size_t lds = (size_t)(3 * kmax + 1) * (1 << LOGQ) * sizeof(float);
+    hipLaunchKernelGGL(k_logsp_check<LOGQ>, dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, kmax, v2c, c2v);
+  }
+  static void var(const DevCode& cd, int nf, const int* alist, const float* llr, const float* c2v, float* v2c,
+                  uint8_t* hard, uint8_t* fsw, int first, hipStream_t s) {
+    const long items = (long)nf * cd.N;
+    if (items == 0) return;
+    hipLaunchKernelGGL(k_logsp_var<LOGQ>, dim3(grid(items)), dim3(64), 0, s, cd, nf, alist, llr, c2v, v2c, hard,
+                       fsw, first);
+  }
+};
+
+template <class Fn>
+bool dispatch_logsp(int m, Fn&& fn) {
+  switch (m) {
+    case 2: fn(LogSp<2>{}); return true;
+    case 3: fn(LogSp<3>{}); return true;
+    case 4: fn(LogSp<4>{}); return true;
+    case 5: fn(LogSp<5>{}); return true;
+    case 6: fn(LogSp<6>{}); return true;
+    case 7: fn(LogSp<7>{}); return true;
+    case 8: fn(LogSp<8>{}); return true;
+    default: return false;
+  }
+}
+
 template <class Fn>
 bool dispatch(int m, int kmax, int logr, Fn&& fn) {
   switch (m) {
@@ -244,6 +283,7 @@ struct PlainWs {
   uint32_t* unsat;
   uint32_t* mism;
   uint32_t* count;
+  int* alist;  // LOGSP: frames still active after the last retirement
 };
 struct FusedWs {
   float* prior;  // [F][N][m] tanh(L/2)
@@ -268,7 +308,10 @@ size_t plain_layout(const ldpc_fd_code_s* c, int F, char* base, PlainWs* w) {
   char* p4 = take((size_t)F * 4);
   char* p5 = take((size_t)F * 4);
   char* p6 = take(4);
-  if (w) *w = PlainWs{(float*)p0, (float*)p1, (uint8_t*)p2, (uint32_t*)p3, (uint32_t*)p4, (uint32_t*)p5, (uint32_t*)p6};
+  char* p7 = take((size_t)F * 4);
+  if (w)
+    *w = PlainWs{(float*)p0, (float*)p1, (uint8_t*)p2, (uint32_t*)p3, (uint32_t*)p4, (uint32_t*)p5, (uint32_t*)p6,
+                 (int*)p7};
   return off;
 }
 
@@ -498,8 +541,8 @@ int32_t ldpc_fd_code_info(ldpc_fd_code c, int32_t* M, int32_t* N, int32_t* m, in
 int32_t ldpc_fd_workspace_bytes(ldpc_fd_code c, int32_t frames, int32_t prec, int32_t mode, int64_t* bytes) {
   if (!c || !bytes || frames < 0) return fail(LDPC_FD_E_INVALID, "bad argument");
   if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
-  if (mode == LDPC_FD_MODE_PLAIN) {
-    if (prec != LDPC_FD_FP32) return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN decoder stores FP32 messages only");
+  if (mode == LDPC_FD_MODE_PLAIN || mode == LDPC_FD_MODE_LOGSP) {
+    if (prec != LDPC_FD_FP32) return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN and LOGSP decoders store FP32 messages only");
     *bytes = (int64_t)plain_layout(c, frames, nullptr, nullptr);
   } else if (mode == LDPC_FD_MODE_FUSED) {
     *bytes = (int64_t)fused_layout(c, frames, prec, nullptr, nullptr);
@@ -531,6 +574,41 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   hipStream_t s = (hipStream_t)stream;
   const DevCode& cd = c->dev;
   const unsigned fb = cdiv(F, 256);
+  if (mode == LDPC_FD_MODE_LOGSP) {
+    // Flooding rounds over the list of still-active frames: round 1 takes all
+    // F frames in order; each retirement appends the continuing frames to
+    // w.alist (in any order: frames are independent) and the host reads their
+    // count, which sizes the next round's launches.
+    PlainWs w;
+    plain_layout(c, F, (char*)workspace, &w);
+    hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, w.active, w.unsat, w.mism, (int*)nullptr,
+                       (int*)nullptr, iters, status, (int*)nullptr, 0);
+    bool ok = dispatch_logsp(c->m, [&](auto impl) {
+      using I = decltype(impl);
+      timed(LDPC_FD_K_VAR, s, [&] { I::var(cd, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1, s); });
+    });
+    if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+    int nf = F;
+    const int* list = nullptr;
+    for (int ell = 1; ell <= max_iter; ++ell) {
+      dispatch_logsp(c->m, [&](auto impl) {
+        using I = decltype(impl);
+        timed(LDPC_FD_K_CHECK, s, [&] { I::check(cd, nf, list, c->kmax, w.v2c, w.c2v, s); });
+        timed(LDPC_FD_K_VAR, s, [&] { I::var(cd, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0, s); });
+      });
+      launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
+      HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
+      hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,
+                         iters, status, w.count, w.alist);
+      int left = 0;
+      if ((rc = read_count(w.count, s, &left))) return rc;
+      if (left == 0) break;
+      nf = left;
+      list = w.alist;
+    }
+    HIP_TRY(hipGetLastError());
+    return LDPC_FD_OK;
+  }
   if (mode == LDPC_FD_MODE_PLAIN) {
     PlainWs w;
     plain_layout(c, F, (char*)workspace, &w);
@@ -550,7 +628,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
       hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,
-                         iters, status, w.count);
+                         iters, status, w.count, (int*)nullptr);
       int left = 0;
       if ((rc = read_count(w.count, s, &left))) return rc;
       if (left == 0) break;
@@ -713,13 +791,16 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   if (F == 0) return LDPC_FD_OK;
   if (!llr || !c2v_out) return fail(LDPC_FD_E_INVALID, "NULL llr or c2v_out");
   if (c2v_in && (!hard || !fsynd || !synd)) return fail(LDPC_FD_E_INVALID, "decision outputs required");
-  if (mode == LDPC_FD_MODE_PLAIN && !v2c_out) return fail(LDPC_FD_E_INVALID, "PLAIN round needs v2c_out");
+  if ((mode == LDPC_FD_MODE_PLAIN || mode == LDPC_FD_MODE_LOGSP) && !v2c_out)
+    return fail(LDPC_FD_E_INVALID, "PLAIN and LOGSP rounds need v2c_out");
   if (mode == LDPC_FD_MODE_FUSED && v2c_out) return fail(LDPC_FD_E_INVALID, "FUSED round does not form v2c_out");
   if (mode == LDPC_FD_MODE_FUSED && c->precise && prec == LDPC_FD_BF16)
     return fail(LDPC_FD_E_UNSUPPORTED, "the FP64 variable node needs FP32 or FP16 storage");
-  if (mode != LDPC_FD_MODE_PLAIN && mode != LDPC_FD_MODE_FUSED) return fail(LDPC_FD_E_INVALID, "unknown mode");
+  if (mode != LDPC_FD_MODE_PLAIN && mode != LDPC_FD_MODE_FUSED && mode != LDPC_FD_MODE_LOGSP)
+    return fail(LDPC_FD_E_INVALID, "unknown mode");
   if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
-  if (mode == LDPC_FD_MODE_PLAIN && prec != LDPC_FD_FP32) return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN is FP32 only");
+  if (mode != LDPC_FD_MODE_FUSED && prec != LDPC_FD_FP32)
+    return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN and LOGSP are FP32 only");
   hipStream_t s = (hipStream_t)stream;
   const DevCode& cd = c->dev;
   char* tmp = nullptr;
@@ -742,7 +823,12 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, active, unsat, mism, alist, nact, (int32_t*)nullptr,
                      (uint32_t*)nullptr, rnd, c2v_in ? 1 : 0);
   launch_prior(c, F, llr, prior, s);
-  bool ok = dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
+  bool ok = mode == LDPC_FD_MODE_LOGSP ? dispatch_logsp(c->m, [&](auto impl) {
+    using I = decltype(impl);
+    I::var(cd, F, nullptr, llr, c2v_in, v2c_out, hard, fsw, c2v_in ? 0 : 1, s);
+    if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
+    I::check(cd, F, nullptr, c->kmax, v2c_out, c2v_out, s);
+  }) : dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
     using I = decltype(impl);
     if (mode == LDPC_FD_MODE_PLAIN) {
       I::var_plain(cd, F, llr, c2v_in, v2c_out, hard, fsw, nullptr, c2v_in ? 0 : 1, s);

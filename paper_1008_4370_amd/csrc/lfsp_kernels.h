@@ -831,9 +831,10 @@ __global__ void k_init_frames(int F, uint32_t* active, uint32_t* unsat, uint32_t
   if (status) status[f] = 0u;
 }
 
-// PLAIN decoder: stopping rule for round ell over all frames.
+// PLAIN and LOGSP decoders: stopping rule for round ell over all frames; with
+// alist, the frames that continue are appended to it (in counter order).
 __global__ void k_retire_plain(int F, int ell, int max_iter, uint32_t* active, uint32_t* unsat,
-                               uint32_t* mism, int32_t* iters, uint32_t* status, uint32_t* count) {
+                               uint32_t* mism, int32_t* iters, uint32_t* status, uint32_t* count, int* alist) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F || !active[f]) return;
   iters[f] = ell;
@@ -844,7 +845,8 @@ __global__ void k_retire_plain(int F, int ell, int max_iter, uint32_t* active, u
   } else if (ell >= max_iter) {
     active[f] = 0u;
   } else {
-    atomicAdd(count, 1u);
+    const uint32_t slot = atomicAdd(count, 1u);
+    if (alist) alist[slot] = f;
   }
   status[f] = st;
   unsat[f] = 0u;

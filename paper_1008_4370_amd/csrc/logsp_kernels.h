@@ -1,0 +1,300 @@
+// The conventional log-domain sum-product decoder (Sec. 2.2), built as the
+// comparison the paper makes against the Log-Fourier SP (Table 1): messages
+// are log2 pmfs in the probability domain, the check node forms each extrinsic
+// message as the (k-1)-fold XOR convolution of the other messages (the "(k-1)-
+// fold CONV x k" of Table 1, via forward and backward partial convolutions,
+// 3(k-2) pairwise convolutions of q^2 log-sum-exp terms each), and the
+// variable node adds log vectors ("2-term ADD x 2").  One wavefront per
+// (frame, node); symbol x of a vector lives on lane x mod 64 (q/64 symbols per
+// lane for q > 64; lanes >= q idle for q < 64).  Log values are clamped to
+// [-kLsFloor, 0] after normalisation to max 0.
+#pragma once
+#include "lfsp_kernels.h"
+
+namespace ldpcfd {
+
+constexpr float kLsFloor = 200.0f;
+
+template <int LOGQ>
+struct LsGeo {
+  static constexpr int Q = 1 << LOGQ;
+  static constexpr int X = Q >= 64 ? Q / 64 : 1;  // symbols per lane
+};
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) v = __builtin_fmaxf(v, __shfl_xor(v, s));
+  return v;
+}
+
+__device__ __forceinline__ int gf_mul(const DevCode& cd, int a, int x) {
+  return (a && x) ? cd.gexp[cd.glog[a] + cd.glog[x]] : 0;
+}
+
+// Pairwise convolution of two rows held in the linear domain:
+// out(x) = sum_a f(a) g(a ^ x), scaled to maximum 1.  Since f = 2^lf and
+// g = 2^lg, log2 out is the log-convolution of lf and lg (log2 sum_a
+// 2^(lf(a) + lg(a ^ x))) less its maximum; evaluating it as a sum of products
+// of exponentials taken once per entry costs q^2 FMAs instead of q^2
+// exponentials.  Both rows have maximum 1, so the sum has a term equal to 1 and
+// none above it: nothing overflows, and the scaling keeps every partial
+// convolution away from underflow.
+//
+// Register tiling: a lane owns the four outputs x0..x0+3 (x0 = 4 xb) and one
+// of S slices of the a-range, in blocks of four: for a = A + s (A, x0
+// multiples of 4) g(a ^ (x0 + r)) = g((A ^ x0) + (s ^ r)), so one 16-byte read
+// of f and one of g feed 16 FMAs.  The S partial sums of an output group sit
+// on adjacent lanes and are added by XOR shuffles.  f, g, out: LDS rows of Q
+// floats, 16-byte aligned (out distinct from f, g).
+template <int LOGQ>
+__device__ __forceinline__ void ls_conv(const float* f, const float* g, float* out) {
+  constexpr int Q = 1 << LOGQ, NB = Q / 4;
+  constexpr int S = (256 / Q) < NB ? (256 / Q) : NB;  // slices of the a-range
+  constexpr int LANES = NB * S, PER = NB / S;
+  const int lane = lane_id();
+  const int xb = lane / S, sp = lane % S, x0 = 4 * xb;
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+  if (lane < LANES) {
+#pragma unroll 4
+    for (int t = 0; t < PER; ++t) {
+      const int A = 4 * (sp + S * t);
+      const float4 fa = *reinterpret_cast<const float4*>(f + A);
+      const float4 ga = *reinterpret_cast<const float4*>(g + (A ^ x0));
+      a0 = __builtin_fmaf(fa.x, ga.x, __builtin_fmaf(fa.y, ga.y, __builtin_fmaf(fa.z, ga.z, __builtin_fmaf(fa.w, ga.w, a0))));
+      a1 = __builtin_fmaf(fa.x, ga.y, __builtin_fmaf(fa.y, ga.x, __builtin_fmaf(fa.z, ga.w, __builtin_fmaf(fa.w, ga.z, a1))));
+      a2 = __builtin_fmaf(fa.x, ga.z, __builtin_fmaf(fa.y, ga.w, __builtin_fmaf(fa.z, ga.x, __builtin_fmaf(fa.w, ga.y, a2))));
+      a3 = __builtin_fmaf(fa.x, ga.w, __builtin_fmaf(fa.y, ga.z, __builtin_fmaf(fa.z, ga.y, __builtin_fmaf(fa.w, ga.x, a3))));
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < S; o <<= 1) {
+    a0 += __shfl_xor(a0, o);
+    a1 += __shfl_xor(a1, o);
+    a2 += __shfl_xor(a2, o);
+    a3 += __shfl_xor(a3, o);
+  }
+  const float mx = __builtin_fmaxf(__builtin_fmaxf(a0, a1), __builtin_fmaxf(a2, a3));
+  const float sc = __builtin_amdgcn_rcpf(wave_max(mx));
+  __syncthreads();
+  if (lane < LANES && sp == 0)
+    *reinterpret_cast<float4*>(out + x0) = make_float4(a0 * sc, a1 * sc, a2 * sc, a3 * sc);
+  __syncthreads();
+}
+
+// CHECK TO VARIABLE (Sec. 2.2, Eq. (2)) for the frames alist[0..nf) (frames
+// 0..nf-1 when alist is NULL): from the log2
+// pmfs v2c[f][e][x] (variable coordinates, maximum 0) to c2v[f][e][x].  The
+// incoming rows are exponentiated once on load, the forward/backward partial
+// convolutions run on linear rows of maximum 1, and each outgoing row is taken
+// back to log2 (less its maximum, floored).  LDS per wavefront (3 kmax + 1) Q
+// floats: the label-mapped inputs, the forward and the backward partials, kmax
+// rows each, and one output row.
+template <int LOGQ>
+__global__ __launch_bounds__(64) void k_logsp_check(DevCode cd, int nf, const int* __restrict__ alist, int kmax,
+                                                    const float* __restrict__ v2c, float* __restrict__ c2v) {
+  using G = LsGeo<LOGQ>;
+  extern __shared__ float ls[];
+  float* in = ls;                       // [kmax][Q]
+  float* fw = ls + kmax * G::Q;         // [kmax][Q]
+  float* bw = ls + 2 * kmax * G::Q;     // [kmax][Q]
+  float* ob = ls + 3 * kmax * G::Q;     // [Q]
+  const int lane = threadIdx.x;
+  const long items = (long)nf * cd.M;
+  for (long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int fi = (int)(it / cd.M), c = (int)(it % cd.M);
+    const int f = alist ? alist[fi] : fi;
+    const int e0 = cd.row_ptr[c], deg = cd.row_ptr[c + 1] - e0;
+    if (deg == 0) continue;
+    // label maps: p~_vc(x) = p_vc(h^-1 x)
+    for (int j = 0; j < deg; ++j) {
+      const int e = e0 + j;
+      const int hinv = cd.ginv[cd.e_label[e]];
+      const float* src = v2c + ((size_t)f * cd.E + e) * G::Q;
+#pragma unroll
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int x = lane + 64 * xj;
+        if (x < G::Q) in[j * G::Q + x] = __builtin_amdgcn_exp2f(src[gf_mul(cd, hinv, x)]);
+      }
+    }
+    __syncthreads();
+    // forward partials fw[j] = in[0] (x) ... (x) in[j], backward bw[j] = in[j] (x) ... (x) in[deg-1]
+#pragma unroll
+    for (int xj = 0; xj < G::X; ++xj) {
+      const int x = lane + 64 * xj;
+      if (x < G::Q) {
+        fw[x] = in[x];
+        bw[(deg - 1) * G::Q + x] = in[(deg - 1) * G::Q + x];
+      }
+    }
+    __syncthreads();
+    for (int j = 1; j <= deg - 2; ++j) ls_conv<LOGQ>(fw + (j - 1) * G::Q, in + j * G::Q, fw + j * G::Q);
+    for (int j = deg - 2; j >= 1; --j) ls_conv<LOGQ>(in + j * G::Q, bw + (j + 1) * G::Q, bw + j * G::Q);
+    for (int j = 0; j < deg; ++j) {
+      const float* o;
+      if (deg == 1) {  // no other edge: the identity of the convolution, mass at 0
+#pragma unroll
+        for (int xj = 0; xj < G::X; ++xj) {
+          const int x = lane + 64 * xj;
+          if (x < G::Q) ob[x] = x == 0 ? 1.0f : 0.0f;
+        }
+        __syncthreads();
+        o = ob;
+      } else if (j == 0) {
+        o = bw + G::Q;
+      } else if (j == deg - 1) {
+        o = fw + (deg - 2) * G::Q;
+      } else {
+        ls_conv<LOGQ>(fw + (j - 1) * G::Q, bw + (j + 1) * G::Q, ob);
+        o = ob;
+      }
+      // p_cv(x) = p~_cv(h x), as log2 less the row maximum
+      const int e = e0 + j;
+      const int h = cd.e_label[e];
+      float v[G::X];
+      float mx = 0.0f;
+#pragma unroll
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int x = lane + 64 * xj;
+        v[xj] = x < G::Q ? o[gf_mul(cd, h, x)] : 0.0f;
+        mx = __builtin_fmaxf(mx, v[xj]);
+      }
+      const float lmx = __builtin_amdgcn_logf(wave_max(mx));
+      float* dst = c2v + ((size_t)f * cd.E + e) * G::Q;
+#pragma unroll
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int x = lane + 64 * xj;
+        if (x < G::Q) dst[x] = __builtin_fmaxf(__builtin_amdgcn_logf(v[xj]) - lmx, -kLsFloor);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// VARIABLE TO CHECK and TENTATIVE DECISION (Sec. 2.2) for the frames listed as
+// for the check node:
+// log2 p_v^(0)(x) = sum_i log2 Pr(b_i = x_i | y) from the LLRs; with first != 0
+// the message to each check is that prior (round 0, no decision); otherwise
+// the message to each check is the prior plus the other check's message, and
+// the posterior (prior plus both messages) gives the bitwise-MAP symbol and the
+// Fourier syndrome word of each edge: the signs of the posterior's transform
+// at e_i (bit marginals of x) and at M_h^T e_i (bit marginals of h x).
+template <int LOGQ>
+__global__ __launch_bounds__(64) void k_logsp_var(DevCode cd, int nf, const int* __restrict__ alist,
+                                                  const float* __restrict__ llr, const float* __restrict__ c2v,
+                                                  float* __restrict__ v2c, uint8_t* __restrict__ hard,
+                                                  uint8_t* __restrict__ fsw, int first) {
+  using G = LsGeo<LOGQ>;
+  const int lane = threadIdx.x;
+  const long items = (long)nf * cd.N;
+  for (long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int fi = (int)(it / cd.N), v = (int)(it % cd.N);
+    const int f = alist ? alist[fi] : fi;
+    const int e1 = cd.v_edges[2 * v], e2 = cd.v_edges[2 * v + 1];
+    const float* l = llr + ((size_t)f * cd.N + v) * LOGQ;
+    const float* m1 = c2v + ((size_t)f * cd.E + e1) * G::Q;
+    const float* m2 = c2v + ((size_t)f * cd.E + e2) * G::Q;
+    float lg[LOGQ];
+#pragma unroll
+    for (int i = 0; i < LOGQ; ++i) lg[i] = l[i];
+    float a1[G::X], a2[G::X];
+    float mx1 = -3.0e38f, mx2 = -3.0e38f;
+#pragma unroll
+    for (int xj = 0; xj < G::X; ++xj) {
+      const int x = lane + 64 * xj;
+      a1[xj] = a2[xj] = -3.0e38f;
+      if (x < G::Q) {
+        // log2 sigma(t) = -log2(1 + 2^u), u = -t log2 e, t = L_i for bit 0 and -L_i for bit 1
+        float s = 0.0f;
+#pragma unroll
+        for (int i = 0; i < LOGQ; ++i) {
+          const float u = ((x >> i) & 1) ? 1.4426950408889634f * lg[i] : -1.4426950408889634f * lg[i];
+          s -= u > 0.0f ? u + __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(-u))
+                        : __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(u));
+        }
+        if (first) {
+          a1[xj] = a2[xj] = s;
+        } else {
+          a1[xj] = s + m2[x];  // to the check of e1: prior and the message from the check of e2
+          a2[xj] = s + m1[x];
+        }
+        mx1 = __builtin_fmaxf(mx1, a1[xj]);
+        mx2 = __builtin_fmaxf(mx2, a2[xj]);
+      }
+    }
+    mx1 = wave_max(mx1);
+    mx2 = wave_max(mx2);
+#pragma unroll
+    for (int xj = 0; xj < G::X; ++xj) {
+      const int x = lane + 64 * xj;
+      if (x < G::Q) {
+        v2c[((size_t)f * cd.E + e1) * G::Q + x] = __builtin_fmaxf(a1[xj] - mx1, -kLsFloor);
+        v2c[((size_t)f * cd.E + e2) * G::Q + x] = __builtin_fmaxf(a2[xj] - mx2, -kLsFloor);
+      }
+    }
+    if (first) continue;
+    // posterior in the linear domain (maximum 1), then its transform P(z) at
+    // z = lane + 64 j: butterflies over the in-register index, then over lanes
+    float p[G::X];
+    float mp = -3.0e38f;
+#pragma unroll
+    for (int xj = 0; xj < G::X; ++xj) {
+      const int x = lane + 64 * xj;
+      p[xj] = -3.0e38f;
+      if (x < G::Q) {
+        p[xj] = a1[xj] + m1[x];
+        mp = __builtin_fmaxf(mp, p[xj]);
+      }
+    }
+    mp = wave_max(mp);
+#pragma unroll
+    for (int xj = 0; xj < G::X; ++xj) {
+      const int x = lane + 64 * xj;
+      p[xj] = x < G::Q ? __builtin_amdgcn_exp2f(p[xj] - mp) : 0.0f;
+    }
+#pragma unroll
+    for (int hs = 1; hs < G::X; hs <<= 1) {
+#pragma unroll
+      for (int xj = 0; xj < G::X; ++xj) {
+        if (xj & hs) continue;
+        const float u = p[xj], w = p[xj + hs];
+        p[xj] = u + w;
+        p[xj + hs] = u - w;
+      }
+    }
+#pragma unroll
+    for (int sh = 1; sh < (G::Q < 64 ? G::Q : 64); sh <<= 1) {
+#pragma unroll
+      for (int xj = 0; xj < G::X; ++xj) {
+        const float o = __shfl_xor(p[xj], sh);
+        p[xj] = (lane & sh) ? o - p[xj] : p[xj] + o;
+      }
+    }
+    // sign bits of P, one 64-bit ballot per in-register index; the decision
+    // reads them at e_i (bit marginals of x) and at M_h^T e_i (those of h x)
+    uint64_t neg[G::X];
+#pragma unroll
+    for (int xj = 0; xj < G::X; ++xj) neg[xj] = __ballot(p[xj] < 0.0f);
+    auto sign_at = [&](int z) {
+      uint64_t w = neg[0];
+#pragma unroll
+      for (int xj = 1; xj < G::X; ++xj)
+        if ((z >> 6) == xj) w = neg[xj];
+      return (int)((w >> (z & 63)) & 1);
+    };
+    const uint64_t c1 = cd.colsT[cd.e_label[e1]], c2 = cd.colsT[cd.e_label[e2]];
+    int hd = 0, w1 = 0, w2 = 0;
+#pragma unroll
+    for (int i = 0; i < LOGQ; ++i) {
+      hd |= sign_at(1 << i) << i;
+      w1 |= sign_at((int)((c1 >> (8 * i)) & 0xff)) << i;
+      w2 |= sign_at((int)((c2 >> (8 * i)) & 0xff)) << i;
+    }
+    if (lane == 0) {
+      hard[(size_t)f * cd.N + v] = (uint8_t)hd;
+      fsw[(size_t)f * cd.E + e1] = (uint8_t)w1;
+      fsw[(size_t)f * cd.E + e2] = (uint8_t)w2;
+    }
+  }
+}
+
+}  // namespace ldpcfd
