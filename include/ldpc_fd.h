@@ -1,6 +1,6 @@
 /*
  * ldpc_fd.h -- C ABI of libldpcfd.so, a gfx950 (MI355X) decoder for non-binary
- * LDPC codes over GF(2^m) with column weight 2, using the Log-Fourier
+ * LDPC codes over GF(2^m), built for column weight 2, using the Log-Fourier
  * sum-product (LF-SP) algorithm of K. Kasai and K. Sakaniwa, "Fourier Domain
  * Decoding Algorithm of Non-Binary LDPC codes for Parallel Implementation",
  * IEICE Trans. Fundamentals 93(11), 2010 (arXiv:1008.4370).
@@ -13,9 +13,13 @@
  *   polynomial prim_poly.
  * Code: H is M x N over GF(2^m), given in compressed-row form (row_ptr, col,
  *   val).  Edge e is the e-th nonzero of H in row-major order; all per-edge
- *   arrays use this check-major order.  Every column must have exactly two
- *   nonzeros (the (j=2,k) codes the method is built for, Sec. 1 and Sec. 4);
- *   rows may have different weights (>= 2).
+ *   arrays use this check-major order.  Columns have weight 1..16 and rows
+ *   2..16.  The fused decoder, the decoding pool, symbol-prior decoding and
+ *   the decode-time posteriors take codes whose every column has weight 2
+ *   (the (2,k) codes the method is built for, Sec. 1 and Sec. 4); the PLAIN
+ *   and LOGSP decoders and the round and imported-state posterior entry
+ *   points also take other column weights (the extension to irregular codes
+ *   noted in Sec. 2), and return E_UNSUPPORTED otherwise.
  * Channel: llr[f][v][i] = ln Pr(b=0|y)/Pr(b=1|y) for bit i (0-based, the
  *   coefficient of alpha^i) of symbol v of frame f, FP32, device memory,
  *   layout [frames][N][m] contiguous.  The symbol prior is the product of the
@@ -47,7 +51,7 @@ typedef struct ldpc_fd_code_s *ldpc_fd_code;
 enum {
   LDPC_FD_OK = 0,
   LDPC_FD_E_INVALID = -1,     /* bad argument or malformed H */
-  LDPC_FD_E_UNSUPPORTED = -2, /* column weight != 2, m outside 2..8, ... */
+  LDPC_FD_E_UNSUPPORTED = -2, /* m outside 2..8, weight above 16, a mode the code cannot use */
   LDPC_FD_E_NOMEM = -3,       /* allocation failed or workspace too small */
   LDPC_FD_E_HIP = -4          /* a HIP runtime call failed */
 };
@@ -58,7 +62,12 @@ enum { LDPC_FD_FP32 = 0, LDPC_FD_FP16 = 1, LDPC_FD_BF16 = 2 };
 /* Decoder variants (PLAIN and FUSED: identical results up to rounding order):
  *  PLAIN: one kernel per node type per round, flooding schedule of Sec. 2
  *         (check-to-variable, variable-to-check, tentative decision), all frames
- *         processed until the host sees every frame stopped.
+ *         processed until the host sees every frame stopped.  For codes with
+ *         other column weights j the variable node forms the j-fold
+ *         log-convolution of Sec. 3.2 through the convolution theorem (each
+ *         message to the probability domain by Gamma^-1 and a Hadamard
+ *         transform, products, back by a Hadamard transform and Gamma), over
+ *         the list of still-active frames.
  *  FUSED: one pass per round over the checks; each pass recomputes the
  *         variable-to-check messages from the stored check-to-variable state,
  *         forms the tentative decision of the previous round, compacts the list
@@ -87,8 +96,9 @@ enum { LDPC_FD_MODE_PLAIN = 0, LDPC_FD_MODE_FUSED = 1, LDPC_FD_MODE_LOGSP = 2 };
  *   x^8+x^4+x^3+x^2+1).
  * out: receives the handle; owns device tables until ldpc_fd_destroy_code.
  * Errors: E_INVALID (bad CSR, label 0 or >= 2^m, duplicate (c,v), row weight
- *   < 2, non-primitive prim_poly), E_UNSUPPORTED (a column weight != 2, m
- *   outside 2..8, row weight > 16), E_HIP / E_NOMEM on device allocation. */
+ *   < 2, a column of weight 0, non-primitive prim_poly), E_UNSUPPORTED (m
+ *   outside 2..8, row or column weight > 16), E_HIP / E_NOMEM on device
+ *   allocation. */
 int32_t ldpc_fd_create_code(int32_t M, int32_t N, int32_t m, const int32_t *row_ptr,
                             const int32_t *col, const uint16_t *val, uint32_t prim_poly,
                             ldpc_fd_code *out);

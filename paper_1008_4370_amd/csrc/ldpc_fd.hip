@@ -37,6 +37,10 @@ const uint32_t kDefaultPoly[9] = {0, 0x3, 0x7, 0xB, 0x13, 0x25, 0x43, 0x89, 0x11
 
 struct ldpc_fd_code_s {
   int M = 0, N = 0, m = 0, q = 0, E = 0, kmax = 0;
+  // largest column weight; regular: every column has weight 2 (the (2,k)
+  // codes the fused decoder, the pool and the decode-time posteriors serve)
+  int jmax = 0;
+  bool regular = true;
   uint32_t poly = 0;
   // tuning (ldpc_fd_set_tuning): log2 entries per lane, fused grid cap, rounds per
   // host check, replay of captured round chunks
@@ -233,11 +237,22 @@ struct LogSp {
     const size_t lds = (size_t)(3 * kmax + 1) * (1 << LOGQ) * sizeof(float);
     hipLaunchKernelGGL(k_logsp_check<LOGQ>, dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, kmax, v2c, c2v);
   }
-  static void var(const DevCode& cd, int nf, const int* alist, const float* llr, const float* c2v, float* v2c,
-                  uint8_t* hard, uint8_t* fsw, int first, hipStream_t s) {
+  static void var(const DevCode& cd, int jmax, int nf, const int* alist, const float* llr, const float* c2v,
+                  float* v2c, uint8_t* hard, uint8_t* fsw, int first, hipStream_t s) {
     const long items = (long)nf * cd.N;
     if (items == 0) return;
-    hipLaunchKernelGGL(k_logsp_var<LOGQ>, dim3(grid(items)), dim3(64), 0, s, cd, nf, alist, llr, c2v, v2c, hard,
+    const size_t lds = (size_t)jmax * (1 << LOGQ) * sizeof(float);
+    hipLaunchKernelGGL(k_logsp_var<LOGQ>, dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, llr, c2v, v2c, hard,
+                       fsw, first);
+  }
+  // Log-Fourier variable node for any column weight (PLAIN decoder, codes
+  // that are not (2,k)); same arguments as var
+  static void var_gen(const DevCode& cd, int jmax, int nf, const int* alist, const float* llr, const float* c2v,
+                      float* v2c, uint8_t* hard, uint8_t* fsw, int first, hipStream_t s) {
+    const long items = (long)nf * cd.N;
+    if (items == 0) return;
+    const size_t lds = (size_t)jmax * (1 << LOGQ) * sizeof(float);
+    hipLaunchKernelGGL(k_var_gen<LOGQ>, dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, llr, c2v, v2c, hard,
                        fsw, first);
   }
 };
@@ -456,10 +471,15 @@ int32_t ldpc_fd_create_code(int32_t M, int32_t N, int32_t m, const int32_t* row_
       colw[col[e]]++;
     }
   }
-  for (int v = 0; v < N; ++v)
-    if (colw[v] != 2)
-      return fail(LDPC_FD_E_UNSUPPORTED, "column " + std::to_string(v) + " has weight " + std::to_string(colw[v]) + " (need 2)");
+  int jmax = 0;
+  bool regular = true;
+  for (int v = 0; v < N; ++v) {
+    if (colw[v] < 1) return fail(LDPC_FD_E_INVALID, "column " + std::to_string(v) + " has weight 0");
+    jmax = std::max(jmax, colw[v]);
+    regular = regular && colw[v] == 2;
+  }
   if (kmax > 16) return fail(LDPC_FD_E_UNSUPPORTED, "row weight above 16");
+  if (jmax > 16) return fail(LDPC_FD_E_UNSUPPORTED, "column weight above 16");
   const uint32_t poly = prim_poly ? prim_poly : kDefaultPoly[m];
   if ((poly >> m) != 1u) return fail(LDPC_FD_E_INVALID, "prim_poly must have degree m");
   // field tables from the primitive polynomial (alpha = x)
@@ -498,15 +518,26 @@ int32_t ldpc_fd_create_code(int32_t M, int32_t N, int32_t m, const int32_t* row_
     el[e] = (uint8_t)val[e];
     epk[e] = (uint32_t)col[e] | ((uint32_t)val[e] << 24);
   }
-  std::vector<int> fill(N, 0);
-  for (int e = 0; e < E; ++e) ve[2 * col[e] + fill[col[e]]++] = e;  // ascending e per variable
-  for (int v = 0; v < N; ++v) {
-    eo[ve[2 * v]] = ve[2 * v + 1];
-    eo[ve[2 * v + 1]] = ve[2 * v];
+  // edges of each variable in ascending order: CSR (v_ptr, v_list) for every
+  // code, and the [N][2] table plus the other-edge map for regular ones
+  std::vector<int> vp(N + 1, 0), vl(E);
+  for (int v = 0; v < N; ++v) vp[v + 1] = vp[v] + colw[v];
+  {
+    std::vector<int> fill(N, 0);
+    for (int e = 0; e < E; ++e) vl[vp[col[e]] + fill[col[e]]++] = e;
+  }
+  if (regular) {
+    for (int v = 0; v < N; ++v) {
+      ve[2 * v] = vl[vp[v]];
+      ve[2 * v + 1] = vl[vp[v] + 1];
+      eo[ve[2 * v]] = ve[2 * v + 1];
+      eo[ve[2 * v + 1]] = ve[2 * v];
+    }
   }
   auto* c = new (std::nothrow) ldpc_fd_code_s();
   if (!c) return fail(LDPC_FD_E_NOMEM, "host allocation failed");
   c->M = M; c->N = N; c->m = m; c->q = q; c->E = E; c->kmax = kmax; c->poly = poly;
+  c->jmax = jmax; c->regular = regular;
   c->logr = kmax > 8 ? 2 : m <= 3 ? m : m <= 7 ? 4 : 3;
   (void)hipGetDevice(&c->device);
   DevCode& d = c->dev;
@@ -515,7 +546,7 @@ int32_t ldpc_fd_create_code(int32_t M, int32_t N, int32_t m, const int32_t* row_
   if ((rc = upload(c, rp, &d.row_ptr)) || (rc = upload(c, ev, &d.e_var)) || (rc = upload(c, eo, &d.e_other)) ||
       (rc = upload(c, el, &d.e_label)) || (rc = upload(c, ve, &d.v_edges)) || (rc = upload(c, colsT, &d.colsT)) ||
       (rc = upload(c, ginv, &d.ginv)) || (rc = upload(c, gexp, &d.gexp)) || (rc = upload(c, glog, &d.glog)) ||
-      (rc = upload(c, epk, &d.e_pack))) {
+      (rc = upload(c, epk, &d.e_pack)) || (rc = upload(c, vp, &d.v_ptr)) || (rc = upload(c, vl, &d.v_list))) {
     delete c;
     return rc;
   }
@@ -564,6 +595,8 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   if (!(llr || prior) || !hard || !synd || !iters || !status || !workspace)
     return fail(LDPC_FD_E_INVALID, "NULL buffer");
   if (prior && mode != LDPC_FD_MODE_FUSED) return fail(LDPC_FD_E_UNSUPPORTED, "symbol priors need the FUSED mode");
+  if (mode == LDPC_FD_MODE_FUSED && !c->regular)
+    return fail(LDPC_FD_E_UNSUPPORTED, "the FUSED decoder needs column weight 2 (PLAIN and LOGSP take any)");
   if (prior && prec != LDPC_FD_FP32) return fail(LDPC_FD_E_UNSUPPORTED, "symbol priors need FP32 storage");
   if (!prior && c->precise && prec == LDPC_FD_BF16 && mode == LDPC_FD_MODE_FUSED)
     return fail(LDPC_FD_E_UNSUPPORTED, "the FP64 variable node needs FP32 or FP16 storage");
@@ -585,7 +618,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
                        (int*)nullptr, iters, status, (int*)nullptr, 0);
     bool ok = dispatch_logsp(c->m, [&](auto impl) {
       using I = decltype(impl);
-      timed(LDPC_FD_K_VAR, s, [&] { I::var(cd, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1, s); });
+      timed(LDPC_FD_K_VAR, s, [&] { I::var(cd, c->jmax, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1, s); });
     });
     if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
     int nf = F;
@@ -594,7 +627,44 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
       dispatch_logsp(c->m, [&](auto impl) {
         using I = decltype(impl);
         timed(LDPC_FD_K_CHECK, s, [&] { I::check(cd, nf, list, c->kmax, w.v2c, w.c2v, s); });
-        timed(LDPC_FD_K_VAR, s, [&] { I::var(cd, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0, s); });
+        timed(LDPC_FD_K_VAR, s, [&] { I::var(cd, c->jmax, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0, s); });
+      });
+      launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
+      HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
+      hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,
+                         iters, status, w.count, w.alist);
+      int left = 0;
+      if ((rc = read_count(w.count, s, &left))) return rc;
+      if (left == 0) break;
+      nf = left;
+      list = w.alist;
+    }
+    HIP_TRY(hipGetLastError());
+    return LDPC_FD_OK;
+  }
+  if (mode == LDPC_FD_MODE_PLAIN && !c->regular) {
+    // Column weights other than 2: the PLAIN check kernel (gated by the
+    // active flags) and the general variable node over the list of active
+    // frames, compacted as in the LOGSP loop.
+    PlainWs w;
+    plain_layout(c, F, (char*)workspace, &w);
+    hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, w.active, w.unsat, w.mism, (int*)nullptr,
+                       (int*)nullptr, iters, status, (int*)nullptr, 0);
+    bool ok = dispatch_logsp(c->m, [&](auto impl) {
+      using I = decltype(impl);
+      timed(LDPC_FD_K_VAR, s, [&] { I::var_gen(cd, c->jmax, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1, s); });
+    });
+    if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+    int nf = F;
+    const int* list = nullptr;
+    for (int ell = 1; ell <= max_iter; ++ell) {
+      dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
+        using I = decltype(impl);
+        timed(LDPC_FD_K_CHECK, s, [&] { I::check_plain(cd, F, w.v2c, w.c2v, w.active, s); });
+      });
+      dispatch_logsp(c->m, [&](auto impl) {
+        using I = decltype(impl);
+        timed(LDPC_FD_K_VAR, s, [&] { I::var_gen(cd, c->jmax, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0, s); });
       });
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
@@ -794,6 +864,8 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   if ((mode == LDPC_FD_MODE_PLAIN || mode == LDPC_FD_MODE_LOGSP) && !v2c_out)
     return fail(LDPC_FD_E_INVALID, "PLAIN and LOGSP rounds need v2c_out");
   if (mode == LDPC_FD_MODE_FUSED && v2c_out) return fail(LDPC_FD_E_INVALID, "FUSED round does not form v2c_out");
+  if (mode == LDPC_FD_MODE_FUSED && !c->regular)
+    return fail(LDPC_FD_E_UNSUPPORTED, "the FUSED decoder needs column weight 2 (PLAIN and LOGSP take any)");
   if (mode == LDPC_FD_MODE_FUSED && c->precise && prec == LDPC_FD_BF16)
     return fail(LDPC_FD_E_UNSUPPORTED, "the FP64 variable node needs FP32 or FP16 storage");
   if (mode != LDPC_FD_MODE_PLAIN && mode != LDPC_FD_MODE_FUSED && mode != LDPC_FD_MODE_LOGSP)
@@ -825,12 +897,18 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   launch_prior(c, F, llr, prior, s);
   bool ok = mode == LDPC_FD_MODE_LOGSP ? dispatch_logsp(c->m, [&](auto impl) {
     using I = decltype(impl);
-    I::var(cd, F, nullptr, llr, c2v_in, v2c_out, hard, fsw, c2v_in ? 0 : 1, s);
+    I::var(cd, c->jmax, F, nullptr, llr, c2v_in, v2c_out, hard, fsw, c2v_in ? 0 : 1, s);
     if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
     I::check(cd, F, nullptr, c->kmax, v2c_out, c2v_out, s);
   }) : dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
     using I = decltype(impl);
-    if (mode == LDPC_FD_MODE_PLAIN) {
+    if (mode == LDPC_FD_MODE_PLAIN && !c->regular) {
+      dispatch_logsp(c->m, [&](auto gen) {
+        decltype(gen)::var_gen(cd, c->jmax, F, nullptr, llr, c2v_in, v2c_out, hard, fsw, c2v_in ? 0 : 1, s);
+      });
+      if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
+      I::check_plain(cd, F, v2c_out, c2v_out, nullptr, s);
+    } else if (mode == LDPC_FD_MODE_PLAIN) {
       I::var_plain(cd, F, llr, c2v_in, v2c_out, hard, fsw, nullptr, c2v_in ? 0 : 1, s);
       if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
       I::check_plain(cd, F, v2c_out, c2v_out, nullptr, s);

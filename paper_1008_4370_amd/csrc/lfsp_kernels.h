@@ -18,14 +18,16 @@ struct DevCode {
   int M, N, E, m;
   const int* row_ptr;      // [M+1]
   const int* e_var;        // [E]
-  const int* e_other;      // [E] the other edge of the same variable
+  const int* e_other;      // [E] the other edge of the same variable (regular codes)
   const uint8_t* e_label;  // [E]
-  const int* v_edges;      // [N][2] (ascending)
+  const int* v_edges;      // [N][2] (ascending; regular codes)
   const uint64_t* colsT;   // [256] byte b of colsT[h] = M_h^T e_b
   const uint8_t* ginv;     // [256]
   const uint8_t* gexp;     // [512]
   const uint16_t* glog;    // [256]
   const uint32_t* e_pack;  // [E] variable | label << 24
+  const int* v_ptr;        // [N+1] edges of variable v: v_list[v_ptr[v] .. v_ptr[v+1])
+  const int* v_list;       // [E] (ascending per variable)
 };
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }

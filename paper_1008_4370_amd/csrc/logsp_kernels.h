@@ -170,130 +170,290 @@ __global__ __launch_bounds__(64) void k_logsp_check(DevCode cd, int nf, const in
   }
 }
 
-// VARIABLE TO CHECK and TENTATIVE DECISION (Sec. 2.2) for the frames listed as
-// for the check node:
-// log2 p_v^(0)(x) = sum_i log2 Pr(b_i = x_i | y) from the LLRs; with first != 0
-// the message to each check is that prior (round 0, no decision); otherwise
-// the message to each check is the prior plus the other check's message, and
-// the posterior (prior plus both messages) gives the bitwise-MAP symbol and the
-// Fourier syndrome word of each edge: the signs of the posterior's transform
-// at e_i (bit marginals of x) and at M_h^T e_i (bit marginals of h x).
+// ---- wavefront-per-variable helpers (symbol x on lane x mod 64) -------------
+
+// Walsh-Hadamard transform of a length-Q vector held as p[j] = v(lane + 64 j):
+// butterflies over the in-register index, then over lanes.  Lanes >= Q (Q <
+// 64) must hold 0 and keep it.
+template <int LOGQ>
+__device__ __forceinline__ void wave_wht(float (&p)[LsGeo<LOGQ>::X]) {
+  using G = LsGeo<LOGQ>;
+  const int lane = lane_id();
+#pragma unroll
+  for (int hs = 1; hs < G::X; hs <<= 1) {
+#pragma unroll
+    for (int xj = 0; xj < G::X; ++xj) {
+      if (xj & hs) continue;
+      const float u = p[xj], w = p[xj + hs];
+      p[xj] = u + w;
+      p[xj + hs] = u - w;
+    }
+  }
+#pragma unroll
+  for (int sh = 1; sh < (G::Q < 64 ? G::Q : 64); sh <<= 1) {
+#pragma unroll
+    for (int xj = 0; xj < G::X; ++xj) {
+      const float o = __shfl_xor(p[xj], sh);
+      p[xj] = (lane & sh) ? o - p[xj] : p[xj] + o;
+    }
+  }
+}
+
+// log2 Pr(X_v = x | y) of the lane's symbols for BPSK LLRs l[0..LOGQ):
+// sum_i log2 sigma(t_i), t_i = L_i for bit i of x = 0 and -L_i for 1,
+// log2 sigma(t) = -log2(1 + 2^u) with u = -t log2 e.
+template <int LOGQ>
+__device__ __forceinline__ void log_prior(const float* __restrict__ l, float (&lp)[LsGeo<LOGQ>::X]) {
+  using G = LsGeo<LOGQ>;
+  const int lane = lane_id();
+  float lg[LOGQ];
+#pragma unroll
+  for (int i = 0; i < LOGQ; ++i) lg[i] = l[i];
+#pragma unroll
+  for (int xj = 0; xj < G::X; ++xj) {
+    const int x = lane + 64 * xj;
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < LOGQ; ++i) {
+      const float u = ((x >> i) & 1) ? 1.4426950408889634f * lg[i] : -1.4426950408889634f * lg[i];
+      s -= u > 0.0f ? u + __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(-u))
+                    : __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(u));
+    }
+    lp[xj] = x < G::Q ? s : -3.0e38f;
+  }
+}
+
+template <int LOGQ>
+__device__ __forceinline__ float row_max(const float (&a)[LsGeo<LOGQ>::X]) {
+  float mx = a[0];
+#pragma unroll
+  for (int xj = 1; xj < LsGeo<LOGQ>::X; ++xj) mx = __builtin_fmaxf(mx, a[xj]);
+  return wave_max(mx);
+}
+
+// TENTATIVE DECISION from the log2 posterior lp (any offset; -3e38 on lanes >=
+// Q): the transform of the linear posterior, then its signs at e_i (the bit
+// marginals of x: bitwise-MAP symbol) and at M_h^T e_i for every edge of v
+// (the bit marginals of h x: Fourier syndrome words), read from ballots.
+template <int LOGQ>
+__device__ __forceinline__ void decide_wave(const DevCode& cd, const float (&lp)[LsGeo<LOGQ>::X], int f, int v,
+                                            int eb, int ee, uint8_t* __restrict__ hard,
+                                            uint8_t* __restrict__ fsw) {
+  using G = LsGeo<LOGQ>;
+  const int lane = lane_id();
+  const float mp = row_max<LOGQ>(lp);
+  float p[G::X];
+#pragma unroll
+  for (int xj = 0; xj < G::X; ++xj) {
+    const int x = lane + 64 * xj;
+    p[xj] = x < G::Q ? __builtin_amdgcn_exp2f(lp[xj] - mp) : 0.0f;
+  }
+  wave_wht<LOGQ>(p);
+  uint64_t neg[G::X];
+#pragma unroll
+  for (int xj = 0; xj < G::X; ++xj) neg[xj] = __ballot(p[xj] < 0.0f);
+  auto sign_at = [&](int z) {
+    uint64_t w = neg[0];
+#pragma unroll
+    for (int xj = 1; xj < G::X; ++xj)
+      if ((z >> 6) == xj) w = neg[xj];
+    return (int)((w >> (z & 63)) & 1);
+  };
+  int hd = 0;
+#pragma unroll
+  for (int i = 0; i < LOGQ; ++i) hd |= sign_at(1 << i) << i;
+  if (lane == 0) hard[(size_t)f * cd.N + v] = (uint8_t)hd;
+  for (int k = eb; k < ee; ++k) {
+    const int e = cd.v_list[k];
+    const uint64_t cm = cd.colsT[cd.e_label[e]];
+    int w = 0;
+#pragma unroll
+    for (int i = 0; i < LOGQ; ++i) w |= sign_at((int)((cm >> (8 * i)) & 0xff)) << i;
+    if (lane == 0) fsw[(size_t)f * cd.E + e] = (uint8_t)w;
+  }
+}
+
+// VARIABLE TO CHECK and TENTATIVE DECISION (Sec. 2.2) of the Log-SP decoder,
+// any column weight j <= 16, for the frames listed as for the check node.
+// With first != 0 the message to each check is the prior (round 0, no
+// decision); otherwise the message to check c is the prior plus the messages
+// from the other checks of v (log domain: a sum), maximum 0, floored, and the
+// posterior (prior plus all messages) gives the decision.  LDS per wavefront:
+// the j incoming rows (jmax rows of Q floats).
 template <int LOGQ>
 __global__ __launch_bounds__(64) void k_logsp_var(DevCode cd, int nf, const int* __restrict__ alist,
                                                   const float* __restrict__ llr, const float* __restrict__ c2v,
                                                   float* __restrict__ v2c, uint8_t* __restrict__ hard,
                                                   uint8_t* __restrict__ fsw, int first) {
   using G = LsGeo<LOGQ>;
+  extern __shared__ float rows[];  // [jmax][Q]
   const int lane = threadIdx.x;
   const long items = (long)nf * cd.N;
   for (long it = blockIdx.x; it < items; it += gridDim.x) {
     const int fi = (int)(it / cd.N), v = (int)(it % cd.N);
     const int f = alist ? alist[fi] : fi;
-    const int e1 = cd.v_edges[2 * v], e2 = cd.v_edges[2 * v + 1];
+    const int eb = cd.v_ptr[v], ee = cd.v_ptr[v + 1];
+    float lp[G::X];
+    log_prior<LOGQ>(llr + ((size_t)f * cd.N + v) * LOGQ, lp);
+    if (first) {
+      const float mx = row_max<LOGQ>(lp);
+      for (int k = eb; k < ee; ++k) {
+        float* dst = v2c + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
+#pragma unroll
+        for (int xj = 0; xj < G::X; ++xj) {
+          const int x = lane + 64 * xj;
+          if (x < G::Q) dst[x] = __builtin_fmaxf(lp[xj] - mx, -kLsFloor);
+        }
+      }
+      continue;
+    }
+    for (int k = eb; k < ee; ++k) {
+      const float* src = c2v + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
+#pragma unroll
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int x = lane + 64 * xj;
+        if (x < G::Q) rows[(k - eb) * G::Q + x] = src[x];
+      }
+    }
+    __syncthreads();
+    for (int k = eb; k < ee; ++k) {
+      float a[G::X];
+#pragma unroll
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int x = lane + 64 * xj;
+        a[xj] = lp[xj];
+        if (x < G::Q)
+          for (int s = eb; s < ee; ++s)
+            if (s != k) a[xj] += rows[(s - eb) * G::Q + x];
+      }
+      const float mx = row_max<LOGQ>(a);
+      float* dst = v2c + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
+#pragma unroll
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int x = lane + 64 * xj;
+        if (x < G::Q) dst[x] = __builtin_fmaxf(a[xj] - mx, -kLsFloor);
+      }
+    }
+    float post[G::X];
+#pragma unroll
+    for (int xj = 0; xj < G::X; ++xj) {
+      const int x = lane + 64 * xj;
+      post[xj] = lp[xj];
+      if (x < G::Q)
+        for (int s = eb; s < ee; ++s) post[xj] += rows[(s - eb) * G::Q + x];
+    }
+    decide_wave<LOGQ>(cd, post, f, v, eb, ee, hard, fsw);
+    __syncthreads();  // rows are rewritten by the next item
+  }
+}
+
+// VARIABLE TO CHECK and TENTATIVE DECISION of the Log-Fourier SP (Sec. 3.2)
+// for any column weight j <= 16 (the PLAIN decoder's variable node for codes
+// that are not (2,k)): Lambda_vc = Lambda_v^(0) [+] (the [+]-sum of Lambda_c'v
+// over the other checks c' of v), normalised to Lambda_vc(0) = (0,0).  The
+// j-fold log-convolution runs through the convolution theorem: each incoming
+// message is taken to the probability domain (Gamma^-1, then a Hadamard
+// transform), the channel pmf and the other messages are multiplied (as sums
+// of log2 values, each clamped at 2^-126), and the product goes back through a
+// Hadamard transform and Gamma.  first != 0: Lambda_v^(0)(z) =
+// Gamma(prod_{i in z} tanh(L_i / 2)) on every edge.  Same frame list and LDS as
+// k_logsp_var; messages in the Log-Fourier word format of the other modes.
+template <int LOGQ>
+__global__ __launch_bounds__(64) void k_var_gen(DevCode cd, int nf, const int* __restrict__ alist,
+                                                const float* __restrict__ llr, const float* __restrict__ c2v,
+                                                float* __restrict__ v2c, uint8_t* __restrict__ hard,
+                                                uint8_t* __restrict__ fsw, int first) {
+  using G = LsGeo<LOGQ>;
+  extern __shared__ float rows[];  // [jmax][Q] log2 of q * p_c'v(x)
+  const int lane = threadIdx.x;
+  const long items = (long)nf * cd.N;
+  for (long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int fi = (int)(it / cd.N), v = (int)(it % cd.N);
+    const int f = alist ? alist[fi] : fi;
+    const int eb = cd.v_ptr[v], ee = cd.v_ptr[v + 1];
     const float* l = llr + ((size_t)f * cd.N + v) * LOGQ;
-    const float* m1 = c2v + ((size_t)f * cd.E + e1) * G::Q;
-    const float* m2 = c2v + ((size_t)f * cd.E + e2) * G::Q;
-    float lg[LOGQ];
+    if (first) {
+      float t[LOGQ];
 #pragma unroll
-    for (int i = 0; i < LOGQ; ++i) lg[i] = l[i];
-    float a1[G::X], a2[G::X];
-    float mx1 = -3.0e38f, mx2 = -3.0e38f;
-#pragma unroll
-    for (int xj = 0; xj < G::X; ++xj) {
-      const int x = lane + 64 * xj;
-      a1[xj] = a2[xj] = -3.0e38f;
-      if (x < G::Q) {
-        // log2 sigma(t) = -log2(1 + 2^u), u = -t log2 e, t = L_i for bit 0 and -L_i for bit 1
-        float s = 0.0f;
-#pragma unroll
-        for (int i = 0; i < LOGQ; ++i) {
-          const float u = ((x >> i) & 1) ? 1.4426950408889634f * lg[i] : -1.4426950408889634f * lg[i];
-          s -= u > 0.0f ? u + __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(-u))
-                        : __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(u));
-        }
-        if (first) {
-          a1[xj] = a2[xj] = s;
-        } else {
-          a1[xj] = s + m2[x];  // to the check of e1: prior and the message from the check of e2
-          a2[xj] = s + m1[x];
-        }
-        mx1 = __builtin_fmaxf(mx1, a1[xj]);
-        mx2 = __builtin_fmaxf(mx2, a2[xj]);
+      for (int i = 0; i < LOGQ; ++i) {
+        const float x = l[i];
+        const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * __builtin_fabsf(x));
+        t[i] = __builtin_copysignf((1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e), x);
       }
-    }
-    mx1 = wave_max(mx1);
-    mx2 = wave_max(mx2);
-#pragma unroll
-    for (int xj = 0; xj < G::X; ++xj) {
-      const int x = lane + 64 * xj;
-      if (x < G::Q) {
-        v2c[((size_t)f * cd.E + e1) * G::Q + x] = __builtin_fmaxf(a1[xj] - mx1, -kLsFloor);
-        v2c[((size_t)f * cd.E + e2) * G::Q + x] = __builtin_fmaxf(a2[xj] - mx2, -kLsFloor);
-      }
-    }
-    if (first) continue;
-    // posterior in the linear domain (maximum 1), then its transform P(z) at
-    // z = lane + 64 j: butterflies over the in-register index, then over lanes
-    float p[G::X];
-    float mp = -3.0e38f;
-#pragma unroll
-    for (int xj = 0; xj < G::X; ++xj) {
-      const int x = lane + 64 * xj;
-      p[xj] = -3.0e38f;
-      if (x < G::Q) {
-        p[xj] = a1[xj] + m1[x];
-        mp = __builtin_fmaxf(mp, p[xj]);
-      }
-    }
-    mp = wave_max(mp);
-#pragma unroll
-    for (int xj = 0; xj < G::X; ++xj) {
-      const int x = lane + 64 * xj;
-      p[xj] = x < G::Q ? __builtin_amdgcn_exp2f(p[xj] - mp) : 0.0f;
-    }
-#pragma unroll
-    for (int hs = 1; hs < G::X; hs <<= 1) {
+      float w[G::X];
 #pragma unroll
       for (int xj = 0; xj < G::X; ++xj) {
-        if (xj & hs) continue;
-        const float u = p[xj], w = p[xj + hs];
-        p[xj] = u + w;
-        p[xj + hs] = u - w;
-      }
-    }
+        const int z = lane + 64 * xj;
+        float p0 = 1.0f;
 #pragma unroll
-    for (int sh = 1; sh < (G::Q < 64 ? G::Q : 64); sh <<= 1) {
+        for (int i = 0; i < LOGQ; ++i)
+          if ((z >> i) & 1) p0 *= t[i];
+        w[xj] = gamma_rel(p0, 0.0f);
+      }
+      for (int k = eb; k < ee; ++k) {
+        float* dst = v2c + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
+#pragma unroll
+        for (int xj = 0; xj < G::X; ++xj) {
+          const int z = lane + 64 * xj;
+          if (z < G::Q) dst[z] = w[xj];
+        }
+      }
+      continue;
+    }
+    float lp[G::X];
+    log_prior<LOGQ>(l, lp);
+    for (int k = eb; k < ee; ++k) {
+      const float* src = c2v + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
+      float p[G::X];
 #pragma unroll
       for (int xj = 0; xj < G::X; ++xj) {
-        const float o = __shfl_xor(p[xj], sh);
-        p[xj] = (lane & sh) ? o - p[xj] : p[xj] + o;
+        const int z = lane + 64 * xj;
+        p[xj] = z < G::Q ? gamma_inv(src[z]) : 0.0f;
+      }
+      wave_wht<LOGQ>(p);
+#pragma unroll
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int x = lane + 64 * xj;
+        if (x < G::Q) rows[(k - eb) * G::Q + x] = __builtin_amdgcn_logf(__builtin_fmaxf(p[xj], 1.17549435e-38f));
       }
     }
-    // sign bits of P, one 64-bit ballot per in-register index; the decision
-    // reads them at e_i (bit marginals of x) and at M_h^T e_i (those of h x)
-    uint64_t neg[G::X];
+    __syncthreads();
+    for (int k = eb; k < ee; ++k) {
+      float a[G::X];
 #pragma unroll
-    for (int xj = 0; xj < G::X; ++xj) neg[xj] = __ballot(p[xj] < 0.0f);
-    auto sign_at = [&](int z) {
-      uint64_t w = neg[0];
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int x = lane + 64 * xj;
+        a[xj] = lp[xj];
+        if (x < G::Q)
+          for (int s = eb; s < ee; ++s)
+            if (s != k) a[xj] += rows[(s - eb) * G::Q + x];
+      }
+      const float mx = row_max<LOGQ>(a);
 #pragma unroll
-      for (int xj = 1; xj < G::X; ++xj)
-        if ((z >> 6) == xj) w = neg[xj];
-      return (int)((w >> (z & 63)) & 1);
-    };
-    const uint64_t c1 = cd.colsT[cd.e_label[e1]], c2 = cd.colsT[cd.e_label[e2]];
-    int hd = 0, w1 = 0, w2 = 0;
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int x = lane + 64 * xj;
+        a[xj] = x < G::Q ? __builtin_amdgcn_exp2f(a[xj] - mx) : 0.0f;
+      }
+      wave_wht<LOGQ>(a);
+      const float y0 = __shfl(a[0], 0);
+      const float lg0 = __builtin_amdgcn_logf(__builtin_fmaxf(y0, 1e-37f));
+      float* dst = v2c + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
 #pragma unroll
-    for (int i = 0; i < LOGQ; ++i) {
-      hd |= sign_at(1 << i) << i;
-      w1 |= sign_at((int)((c1 >> (8 * i)) & 0xff)) << i;
-      w2 |= sign_at((int)((c2 >> (8 * i)) & 0xff)) << i;
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int z = lane + 64 * xj;
+        if (z < G::Q) dst[z] = gamma_rel(a[xj], lg0);
+      }
     }
-    if (lane == 0) {
-      hard[(size_t)f * cd.N + v] = (uint8_t)hd;
-      fsw[(size_t)f * cd.E + e1] = (uint8_t)w1;
-      fsw[(size_t)f * cd.E + e2] = (uint8_t)w2;
+    float post[G::X];
+#pragma unroll
+    for (int xj = 0; xj < G::X; ++xj) {
+      const int x = lane + 64 * xj;
+      post[xj] = lp[xj];
+      if (x < G::Q)
+        for (int s = eb; s < ee; ++s) post[xj] += rows[(s - eb) * G::Q + x];
     }
+    decide_wave<LOGQ>(cd, post, f, v, eb, ee, hard, fsw);
+    __syncthreads();  // rows are rewritten by the next item
   }
 }
 

@@ -97,16 +97,39 @@ def check_degrees(N: int, k: int, j: int = 2, M: int | None = None) -> np.ndarra
     return deg
 
 
+def irregular_var_degrees(N: int, dist: dict, seed: int = 1005) -> np.ndarray:
+    """Column weights for N variables: round(N * fraction) of each weight in
+    `dist` ({weight: fraction}, the largest fraction absorbing the rounding),
+    in a seeded random order."""
+    ws = sorted(dist)
+    counts = {w: int(round(N * dist[w])) for w in ws}
+    top = max(ws, key=lambda w: dist[w])
+    counts[top] += N - sum(counts.values())
+    deg = np.concatenate([np.full(counts[w], w, dtype=np.int64) for w in ws])
+    return np.random.default_rng(seed).permutation(deg)
+
+
 def make_code(N: int, k: int, m: int, seed_graph: int = 1001, seed_labels: int = 1002,
               j: int = 2, M: int | None = None, poly: int | None = None,
-              max_retries: int = 200) -> Code:
+              max_retries: int = 200, var_degrees: np.ndarray | None = None) -> Code:
     """Seeded configuration-model (j, k) Tanner graph without double edges and
-    with labels uniform on the nonzero field elements."""
+    with labels uniform on the nonzero field elements.  With var_degrees the
+    column weights are those (an irregular code); the checks stay near-regular
+    with M = round(E / k) unless M is given."""
     rng = np.random.default_rng(seed_graph)
-    deg_c = check_degrees(N, k, j, M)
+    if var_degrees is None:
+        deg_c = check_degrees(N, k, j, M)
+        var_sock = np.repeat(np.arange(N), j)
+    else:
+        var_degrees = np.asarray(var_degrees, dtype=np.int64)
+        E = int(var_degrees.sum())
+        Mi = int(round(E / k)) if M is None else M
+        base, extra = divmod(E, Mi)
+        deg_c = np.full(Mi, base, dtype=np.int64)
+        deg_c[:extra] += 1
+        var_sock = np.repeat(np.arange(N), var_degrees)
     M = len(deg_c)
     chk_sock = np.repeat(np.arange(M), deg_c)
-    var_sock = np.repeat(np.arange(N), j)
     perm = None
     for _ in range(max_retries):
         p = rng.permutation(len(var_sock))
@@ -257,6 +280,10 @@ WORKLOADS = {
     "gf16_n2048": dict(m=4, k=4, N=2048, frames=3000, ebn0=[2.5], max_iter=100),
     "gf64_n512": dict(m=6, k=6, N=512, frames=6000, ebn0=[2.5], max_iter=100),
     "gf256_n256_k16": dict(m=8, k=16, N=256, frames=2000, ebn0=[2.5], max_iter=100),
+    # irregular column weights (Sec. 2 notes the extension): 70% weight 2,
+    # 20% weight 3, 10% weight 4; near-regular rows of weight ~6
+    "gf64_n1000_irr": dict(m=6, k=6, N=1000, frames=2048, ebn0=[2.0, 2.5, 3.0], max_iter=100,
+                           var_dist={2: 0.7, 3: 0.2, 4: 0.1}),
 }
 
 
@@ -277,7 +304,8 @@ class Batch:
 def make_batch(name: str, frames: int | None = None, ebn0: float | None = None,
                point: int = 0, seed_base: int = 1000) -> Batch:
     w = WORKLOADS[name]
-    code = make_code(w["N"], w["k"], w["m"], seed_graph=seed_base + 1, seed_labels=seed_base + 2)
+    vd = irregular_var_degrees(w["N"], w["var_dist"], seed=seed_base + 5) if "var_dist" in w else None
+    code = make_code(w["N"], w["k"], w["m"], seed_graph=seed_base + 1, seed_labels=seed_base + 2, var_degrees=vd)
     enc = Encoder(code)
     F = w["frames"] if frames is None else frames
     e = w["ebn0"][point] if ebn0 is None else ebn0

@@ -30,7 +30,7 @@ def _create(M, N, m, rp, col, val, poly=0):
 @pytest.mark.parametrize("args,rc,msg", [
     ((1, 2, 1, [0, 2], [0, 1], [1, 1]), d.E_UNSUPPORTED, "m must"),
     ((1, 2, 9, [0, 2], [0, 1], [1, 1]), d.E_UNSUPPORTED, "m must"),
-    ((1, 2, 2, [0, 2], [0, 1], [1, 1]), d.E_UNSUPPORTED, "weight 1"),
+    ((1, 3, 2, [0, 2], [0, 1], [1, 1]), d.E_INVALID, "weight 0"),
     ((2, 2, 2, [0, 2, 4], [0, 1, 0, 1], [1, 4, 1, 1]), d.E_INVALID, "label"),
     ((2, 2, 2, [0, 2, 4], [0, 1, 0, 1], [1, 0, 1, 1]), d.E_INVALID, "label"),
     ((2, 2, 2, [0, 2, 4], [0, 0, 1, 1], [1, 1, 1, 1]), d.E_INVALID, "duplicate"),
@@ -56,3 +56,12 @@ def test_row_weight_limit():
     col = list(range(17)) * 2
     got, err = _create(2, 17, 5, [0, 17, 34], col, [1] * 34)
     assert got == d.E_UNSUPPORTED and "row weight" in err
+
+
+def test_column_weight_limit():
+    """Columns heavier than 16 are rejected before any device allocation; the
+    column weights below that may be irregular."""
+    rp = [2 * r for r in range(18)]
+    col = [x for r in range(17) for x in (0, r + 1)]
+    got, err = _create(17, 18, 3, rp, col, [1] * 34)
+    assert got == d.E_UNSUPPORTED and "column weight" in err
