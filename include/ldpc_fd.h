@@ -80,8 +80,17 @@ enum { LDPC_FD_FP32 = 0, LDPC_FD_FP16 = 1, LDPC_FD_BF16 = 2 };
  *         convolutions of q^2 log-sum-exp terms), the variable node adds log
  *         vectors; flooding schedule and stopping rule as PLAIN.  Same outputs
  *         as the Log-Fourier modes up to rounding; FP32 storage only; the
- *         PRECISE and DECISION_MFMA tuning keys do not apply. */
-enum { LDPC_FD_MODE_PLAIN = 0, LDPC_FD_MODE_FUSED = 1, LDPC_FD_MODE_LOGSP = 2 };
+ *         PRECISE and DECISION_MFMA tuning keys do not apply.
+ *  FSP:   the linear-domain Fourier SP of Sec. 3.1 (the algorithm the
+ *         Log-Fourier SP is derived from): messages are P(z) itself (FP32,
+ *         normalised to P(0) = 1), the check node multiplies the other k-1
+ *         label-mapped messages component-wise, the variable node forms the
+ *         j-fold convolution through the convolution theorem as PLAIN does for
+ *         irregular codes; any column weight, FP32 only.  With the tuning key
+ *         QUANT_BITS the PLAIN, FSP and LOGSP decoders store their messages on a b-bit
+ *         grid (the quantisation comparison that motivates the paper, Sec. 1
+ *         and Sec. 2.2). */
+enum { LDPC_FD_MODE_PLAIN = 0, LDPC_FD_MODE_FUSED = 1, LDPC_FD_MODE_LOGSP = 2, LDPC_FD_MODE_FSP = 3 };
 
 /* status[f] bits */
 #define LDPC_FD_STATUS_CONVERGED 1u /* stopped on a passed codeword test */
@@ -304,10 +313,22 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *     lanes per frame (2^m = 16, 32, 64; elsewhere, and with PRECISE, the FP32
  *     VALU transforms are used).  Decisions can differ from the VALU form only
  *     where a posterior value at a read point is within rounding of zero.
+ *   LDPC_FD_TUNE_QUANT_BITS: b in 3..16 = the PLAIN, FSP and LOGSP decoders (decode
+ *     and round) replace every message they store by the nearest word of a
+ *     b-bit format, emulating b-bit message memory (the arrays stay FP32; the
+ *     bandwidth is not reduced); 0 (default) = off.  PLAIN (Log-Fourier words):
+ *     sign bit plus a (b-1)-bit magnitude -log2|P| on the grid k * step,
+ *     k = 0 .. 2^(b-1) - 1 (nearest, saturating).  FSP (linear P in [-1, 1]):
+ *     b-bit two's complement fixed point with step 2^-(b-1).  LOGSP (log2
+ *     pmfs <= 0): b-bit unsigned -k * step, k = 0 .. 2^b - 1.  FUSED ignores
+ *     it.  Changes results by design.
+ *   LDPC_FD_TUNE_QUANT_STEP: the PLAIN and LOGSP step in units of 2^-12
+ *     (1..65536; default 256, i.e. 1/16).
  * Errors: E_INVALID (unknown key or value), E_UNSUPPORTED (no such variant). */
 enum { LDPC_FD_TUNE_LANE_ENTRIES = 0, LDPC_FD_TUNE_GRID_BLOCKS = 1, LDPC_FD_TUNE_CHUNK = 2,
        LDPC_FD_TUNE_GRAPHS = 3, LDPC_FD_TUNE_TAIL_ENTRIES = 4, LDPC_FD_TUNE_TAIL_FRAMES = 5,
-       LDPC_FD_TUNE_PRECISE = 6, LDPC_FD_TUNE_DECISION_MFMA = 7, LDPC_FD_TUNE_TAIL_SPLIT = 8 };
+       LDPC_FD_TUNE_PRECISE = 6, LDPC_FD_TUNE_DECISION_MFMA = 7, LDPC_FD_TUNE_TAIL_SPLIT = 8,
+       LDPC_FD_TUNE_QUANT_BITS = 9, LDPC_FD_TUNE_QUANT_STEP = 10 };
 int32_t ldpc_fd_set_tuning(ldpc_fd_code code, int32_t key, int32_t value);
 int32_t ldpc_fd_get_tuning(ldpc_fd_code code, int32_t key, int32_t *value);
 

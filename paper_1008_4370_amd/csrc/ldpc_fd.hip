@@ -55,6 +55,9 @@ struct ldpc_fd_code_s {
   // 1: the tentative decision's transforms on the matrix cores (FP16 MFMA,
   // variants with 16 frames per wavefront)
   int mfma = 0;
+  // emulated low-bit message storage of the PLAIN and FSP decoders: bits (0 =
+  // off) and the magnitude step of Log-Fourier words in units of 2^-12
+  int qbits = 0, qstep = 256;
   int device = 0;
   std::vector<void*> allocs;
   DevCode dev{};
@@ -245,15 +248,27 @@ struct LogSp {
     hipLaunchKernelGGL(k_logsp_var<LOGQ>, dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, llr, c2v, v2c, hard,
                        fsw, first);
   }
-  // Log-Fourier variable node for any column weight (PLAIN decoder, codes
-  // that are not (2,k)); same arguments as var
+  // Log-Fourier (lin = false) or linear Fourier (lin = true) variable node for
+  // any column weight; same arguments as var
   static void var_gen(const DevCode& cd, int jmax, int nf, const int* alist, const float* llr, const float* c2v,
-                      float* v2c, uint8_t* hard, uint8_t* fsw, int first, hipStream_t s) {
+                      float* v2c, uint8_t* hard, uint8_t* fsw, int first, hipStream_t s, bool lin = false) {
     const long items = (long)nf * cd.N;
     if (items == 0) return;
     const size_t lds = (size_t)jmax * (1 << LOGQ) * sizeof(float);
-    hipLaunchKernelGGL(k_var_gen<LOGQ>, dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, llr, c2v, v2c, hard,
-                       fsw, first);
+    if (lin)
+      hipLaunchKernelGGL((k_var_gen<LOGQ, true>), dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, llr, c2v, v2c,
+                         hard, fsw, first);
+    else
+      hipLaunchKernelGGL((k_var_gen<LOGQ, false>), dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, llr, c2v,
+                         v2c, hard, fsw, first);
+  }
+  // linear Fourier SP check node (LDPC_FD_MODE_FSP)
+  static void fsp_check(const DevCode& cd, int nf, const int* alist, int kmax, const float* v2c, float* c2v,
+                        hipStream_t s) {
+    const long items = (long)nf * cd.M;
+    if (items == 0) return;
+    const size_t lds = (size_t)2 * kmax * (1 << LOGQ) * sizeof(float);
+    hipLaunchKernelGGL(k_fsp_check<LOGQ>, dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, kmax, v2c, c2v);
   }
 };
 
@@ -360,6 +375,17 @@ int32_t read_count(const void* dptr, hipStream_t s, int* out) {
 }
 
 unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// Emulated low-bit storage (tuning key QUANT_BITS) of F frames' messages:
+// kind 0 for Log-Fourier words, 1 for linear Fourier values, 2 for Log-SP
+// log2 pmfs.
+void launch_quantise(const ldpc_fd_code_s* c, int F, float* msg, int kind, hipStream_t s) {
+  if (!c->qbits) return;
+  const size_t n = (size_t)F * c->E * c->q;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_quantise, dim3((unsigned)std::min<size_t>((n + 255) / 256, 16384)), dim3(256), 0, s, msg, n,
+                     kind, c->qbits, (float)c->qstep / 4096.0f);
+}
 
 // Prior factors tanh(L/2) of every frame, symbol and bit.
 void launch_prior(const ldpc_fd_code_s* c, int F, const float* llr, float* prior, hipStream_t s) {
@@ -572,8 +598,9 @@ int32_t ldpc_fd_code_info(ldpc_fd_code c, int32_t* M, int32_t* N, int32_t* m, in
 int32_t ldpc_fd_workspace_bytes(ldpc_fd_code c, int32_t frames, int32_t prec, int32_t mode, int64_t* bytes) {
   if (!c || !bytes || frames < 0) return fail(LDPC_FD_E_INVALID, "bad argument");
   if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
-  if (mode == LDPC_FD_MODE_PLAIN || mode == LDPC_FD_MODE_LOGSP) {
-    if (prec != LDPC_FD_FP32) return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN and LOGSP decoders store FP32 messages only");
+  if (mode == LDPC_FD_MODE_PLAIN || mode == LDPC_FD_MODE_LOGSP || mode == LDPC_FD_MODE_FSP) {
+    if (prec != LDPC_FD_FP32)
+      return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN, LOGSP and FSP decoders store FP32 messages only");
     *bytes = (int64_t)plain_layout(c, frames, nullptr, nullptr);
   } else if (mode == LDPC_FD_MODE_FUSED) {
     *bytes = (int64_t)fused_layout(c, frames, prec, nullptr, nullptr);
@@ -621,13 +648,16 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
       timed(LDPC_FD_K_VAR, s, [&] { I::var(cd, c->jmax, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1, s); });
     });
     if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+    launch_quantise(c, F, w.v2c, 2, s);
     int nf = F;
     const int* list = nullptr;
     for (int ell = 1; ell <= max_iter; ++ell) {
       dispatch_logsp(c->m, [&](auto impl) {
         using I = decltype(impl);
         timed(LDPC_FD_K_CHECK, s, [&] { I::check(cd, nf, list, c->kmax, w.v2c, w.c2v, s); });
+        launch_quantise(c, F, w.c2v, 2, s);
         timed(LDPC_FD_K_VAR, s, [&] { I::var(cd, c->jmax, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0, s); });
+        launch_quantise(c, F, w.v2c, 2, s);
       });
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
@@ -642,30 +672,43 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     HIP_TRY(hipGetLastError());
     return LDPC_FD_OK;
   }
-  if (mode == LDPC_FD_MODE_PLAIN && !c->regular) {
-    // Column weights other than 2: the PLAIN check kernel (gated by the
-    // active flags) and the general variable node over the list of active
-    // frames, compacted as in the LOGSP loop.
+  if (mode == LDPC_FD_MODE_FSP || (mode == LDPC_FD_MODE_PLAIN && !c->regular)) {
+    // The general variable node over the list of active frames (compacted as
+    // in the LOGSP loop) with, for FSP, the linear check node over the same
+    // list, and otherwise the PLAIN check kernel gated by the active flags
+    // (column weights other than 2).
+    const bool lin = mode == LDPC_FD_MODE_FSP;
+    const int qk = lin ? 1 : 0;
     PlainWs w;
     plain_layout(c, F, (char*)workspace, &w);
     hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, w.active, w.unsat, w.mism, (int*)nullptr,
                        (int*)nullptr, iters, status, (int*)nullptr, 0);
     bool ok = dispatch_logsp(c->m, [&](auto impl) {
       using I = decltype(impl);
-      timed(LDPC_FD_K_VAR, s, [&] { I::var_gen(cd, c->jmax, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1, s); });
+      timed(LDPC_FD_K_VAR, s, [&] { I::var_gen(cd, c->jmax, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1, s, lin); });
     });
     if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+    launch_quantise(c, F, w.v2c, qk, s);
     int nf = F;
     const int* list = nullptr;
     for (int ell = 1; ell <= max_iter; ++ell) {
-      dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
-        using I = decltype(impl);
-        timed(LDPC_FD_K_CHECK, s, [&] { I::check_plain(cd, F, w.v2c, w.c2v, w.active, s); });
-      });
+      if (lin) {
+        dispatch_logsp(c->m, [&](auto impl) {
+          using I = decltype(impl);
+          timed(LDPC_FD_K_CHECK, s, [&] { I::fsp_check(cd, nf, list, c->kmax, w.v2c, w.c2v, s); });
+        });
+      } else {
+        dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
+          using I = decltype(impl);
+          timed(LDPC_FD_K_CHECK, s, [&] { I::check_plain(cd, F, w.v2c, w.c2v, w.active, s); });
+        });
+      }
+      launch_quantise(c, F, w.c2v, qk, s);
       dispatch_logsp(c->m, [&](auto impl) {
         using I = decltype(impl);
-        timed(LDPC_FD_K_VAR, s, [&] { I::var_gen(cd, c->jmax, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0, s); });
+        timed(LDPC_FD_K_VAR, s, [&] { I::var_gen(cd, c->jmax, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0, s, lin); });
       });
+      launch_quantise(c, F, w.v2c, qk, s);
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
       hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,
@@ -688,12 +731,15 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
       using I = decltype(impl);
       timed(LDPC_FD_K_VAR, s, [&] { I::var_plain(cd, F, llr, nullptr, w.v2c, hard, w.fsw, w.active, 1, s); });
     });
+    launch_quantise(c, F, w.v2c, 0, s);
     if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
     for (int ell = 1; ell <= max_iter; ++ell) {
       dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
         using I = decltype(impl);
         timed(LDPC_FD_K_CHECK, s, [&] { I::check_plain(cd, F, w.v2c, w.c2v, w.active, s); });
+        launch_quantise(c, F, w.c2v, 0, s);
         timed(LDPC_FD_K_VAR, s, [&] { I::var_plain(cd, F, llr, w.c2v, w.v2c, hard, w.fsw, w.active, 0, s); });
+        launch_quantise(c, F, w.v2c, 0, s);
       });
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
@@ -861,18 +907,16 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   if (F == 0) return LDPC_FD_OK;
   if (!llr || !c2v_out) return fail(LDPC_FD_E_INVALID, "NULL llr or c2v_out");
   if (c2v_in && (!hard || !fsynd || !synd)) return fail(LDPC_FD_E_INVALID, "decision outputs required");
-  if ((mode == LDPC_FD_MODE_PLAIN || mode == LDPC_FD_MODE_LOGSP) && !v2c_out)
-    return fail(LDPC_FD_E_INVALID, "PLAIN and LOGSP rounds need v2c_out");
+  if (mode != LDPC_FD_MODE_FUSED && !v2c_out) return fail(LDPC_FD_E_INVALID, "PLAIN, LOGSP and FSP rounds need v2c_out");
   if (mode == LDPC_FD_MODE_FUSED && v2c_out) return fail(LDPC_FD_E_INVALID, "FUSED round does not form v2c_out");
   if (mode == LDPC_FD_MODE_FUSED && !c->regular)
     return fail(LDPC_FD_E_UNSUPPORTED, "the FUSED decoder needs column weight 2 (PLAIN and LOGSP take any)");
   if (mode == LDPC_FD_MODE_FUSED && c->precise && prec == LDPC_FD_BF16)
     return fail(LDPC_FD_E_UNSUPPORTED, "the FP64 variable node needs FP32 or FP16 storage");
-  if (mode != LDPC_FD_MODE_PLAIN && mode != LDPC_FD_MODE_FUSED && mode != LDPC_FD_MODE_LOGSP)
-    return fail(LDPC_FD_E_INVALID, "unknown mode");
+  if (mode < LDPC_FD_MODE_PLAIN || mode > LDPC_FD_MODE_FSP) return fail(LDPC_FD_E_INVALID, "unknown mode");
   if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
   if (mode != LDPC_FD_MODE_FUSED && prec != LDPC_FD_FP32)
-    return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN and LOGSP are FP32 only");
+    return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN, LOGSP and FSP are FP32 only");
   hipStream_t s = (hipStream_t)stream;
   const DevCode& cd = c->dev;
   char* tmp = nullptr;
@@ -898,20 +942,31 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   bool ok = mode == LDPC_FD_MODE_LOGSP ? dispatch_logsp(c->m, [&](auto impl) {
     using I = decltype(impl);
     I::var(cd, c->jmax, F, nullptr, llr, c2v_in, v2c_out, hard, fsw, c2v_in ? 0 : 1, s);
+    launch_quantise(c, F, v2c_out, 2, s);
     if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
     I::check(cd, F, nullptr, c->kmax, v2c_out, c2v_out, s);
+    launch_quantise(c, F, c2v_out, 2, s);
   }) : dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
     using I = decltype(impl);
-    if (mode == LDPC_FD_MODE_PLAIN && !c->regular) {
+    if (mode == LDPC_FD_MODE_FSP || (mode == LDPC_FD_MODE_PLAIN && !c->regular)) {
+      const bool lin = mode == LDPC_FD_MODE_FSP;
       dispatch_logsp(c->m, [&](auto gen) {
-        decltype(gen)::var_gen(cd, c->jmax, F, nullptr, llr, c2v_in, v2c_out, hard, fsw, c2v_in ? 0 : 1, s);
+        using GI = decltype(gen);
+        GI::var_gen(cd, c->jmax, F, nullptr, llr, c2v_in, v2c_out, hard, fsw, c2v_in ? 0 : 1, s, lin);
+        launch_quantise(c, F, v2c_out, lin ? 1 : 0, s);
+        if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
+        if (lin)
+          GI::fsp_check(cd, F, nullptr, c->kmax, v2c_out, c2v_out, s);
+        else
+          I::check_plain(cd, F, v2c_out, c2v_out, nullptr, s);
+        launch_quantise(c, F, c2v_out, lin ? 1 : 0, s);
       });
-      if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
-      I::check_plain(cd, F, v2c_out, c2v_out, nullptr, s);
     } else if (mode == LDPC_FD_MODE_PLAIN) {
       I::var_plain(cd, F, llr, c2v_in, v2c_out, hard, fsw, nullptr, c2v_in ? 0 : 1, s);
+      launch_quantise(c, F, v2c_out, 0, s);
       if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
       I::check_plain(cd, F, v2c_out, c2v_out, nullptr, s);
+      launch_quantise(c, F, c2v_out, 0, s);
     } else {
       // Frames at round 1 read buffer 1 and write buffer 0; frames at round 0
       // (no imported state) write buffer 1.  16-bit storage: the imported state
@@ -994,6 +1049,14 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
       if (value != 0 && value != 1) return fail(LDPC_FD_E_INVALID, "tail split: 0 or 1");
       c->split = value;
       return LDPC_FD_OK;
+    case LDPC_FD_TUNE_QUANT_BITS:
+      if (value != 0 && (value < 3 || value > 16)) return fail(LDPC_FD_E_INVALID, "quantisation bits: 0 or 3..16");
+      c->qbits = value;
+      return LDPC_FD_OK;
+    case LDPC_FD_TUNE_QUANT_STEP:
+      if (value < 1 || value > (1 << 16)) return fail(LDPC_FD_E_INVALID, "quantisation step outside 1..65536");
+      c->qstep = value;
+      return LDPC_FD_OK;
     default:
       return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
@@ -1011,6 +1074,8 @@ int32_t ldpc_fd_get_tuning(ldpc_fd_code c, int32_t key, int32_t* value) {
     case LDPC_FD_TUNE_PRECISE: *value = c->precise; return LDPC_FD_OK;
     case LDPC_FD_TUNE_DECISION_MFMA: *value = c->mfma; return LDPC_FD_OK;
     case LDPC_FD_TUNE_TAIL_SPLIT: *value = c->split; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_QUANT_BITS: *value = c->qbits; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_QUANT_STEP: *value = c->qstep; return LDPC_FD_OK;
     default: return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
 }

@@ -358,7 +358,9 @@ __global__ __launch_bounds__(64) void k_logsp_var(DevCode cd, int nf, const int*
 // Hadamard transform and Gamma.  first != 0: Lambda_v^(0)(z) =
 // Gamma(prod_{i in z} tanh(L_i / 2)) on every edge.  Same frame list and LDS as
 // k_logsp_var; messages in the Log-Fourier word format of the other modes.
-template <int LOGQ>
+// LIN: the linear Fourier SP of Sec. 3.1 instead (messages are P itself,
+// normalised to P(0) = 1, no Gamma).
+template <int LOGQ, bool LIN>
 __global__ __launch_bounds__(64) void k_var_gen(DevCode cd, int nf, const int* __restrict__ alist,
                                                 const float* __restrict__ llr, const float* __restrict__ c2v,
                                                 float* __restrict__ v2c, uint8_t* __restrict__ hard,
@@ -388,7 +390,7 @@ __global__ __launch_bounds__(64) void k_var_gen(DevCode cd, int nf, const int* _
 #pragma unroll
         for (int i = 0; i < LOGQ; ++i)
           if ((z >> i) & 1) p0 *= t[i];
-        w[xj] = gamma_rel(p0, 0.0f);
+        w[xj] = LIN ? p0 : gamma_rel(p0, 0.0f);
       }
       for (int k = eb; k < ee; ++k) {
         float* dst = v2c + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(64) void k_var_gen(DevCode cd, int nf, const int* _
 #pragma unroll
       for (int xj = 0; xj < G::X; ++xj) {
         const int z = lane + 64 * xj;
-        p[xj] = z < G::Q ? gamma_inv(src[z]) : 0.0f;
+        p[xj] = z < G::Q ? (LIN ? src[z] : gamma_inv(src[z])) : 0.0f;
       }
       wave_wht<LOGQ>(p);
 #pragma unroll
@@ -435,13 +437,14 @@ __global__ __launch_bounds__(64) void k_var_gen(DevCode cd, int nf, const int* _
         a[xj] = x < G::Q ? __builtin_amdgcn_exp2f(a[xj] - mx) : 0.0f;
       }
       wave_wht<LOGQ>(a);
-      const float y0 = __shfl(a[0], 0);
-      const float lg0 = __builtin_amdgcn_logf(__builtin_fmaxf(y0, 1e-37f));
+      const float y0 = __builtin_fmaxf(__shfl(a[0], 0), 1e-37f);
+      const float lg0 = __builtin_amdgcn_logf(y0);
+      const float r0 = 1.0f / y0;
       float* dst = v2c + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
 #pragma unroll
       for (int xj = 0; xj < G::X; ++xj) {
         const int z = lane + 64 * xj;
-        if (z < G::Q) dst[z] = gamma_rel(a[xj], lg0);
+        if (z < G::Q) dst[z] = LIN ? __builtin_fminf(__builtin_fmaxf(a[xj] * r0, -1.0f), 1.0f) : gamma_rel(a[xj], lg0);
       }
     }
     float post[G::X];
@@ -454,6 +457,104 @@ __global__ __launch_bounds__(64) void k_var_gen(DevCode cd, int nf, const int* _
     }
     decide_wave<LOGQ>(cd, post, f, v, eb, ee, hard, fsw);
     __syncthreads();  // rows are rewritten by the next item
+  }
+}
+
+// M_h^T z for the lane's index z, from cm = colsT[h] (byte b = M_h^T e_b).
+template <int LOGQ>
+__device__ __forceinline__ int apply_mt(uint64_t cm, int z) {
+  int r = 0;
+#pragma unroll
+  for (int b = 0; b < LOGQ; ++b)
+    if ((z >> b) & 1) r ^= (int)((cm >> (8 * b)) & 0xff);
+  return r;
+}
+
+// CHECK TO VARIABLE of the linear Fourier SP (Sec. 3.1): P~_vc(z) =
+// P_vc(M_h^T z); P~_cv(z) = product of P~_v'c(z) over the other edges of the
+// check (component-wise, through prefix and suffix products, no division);
+// P_cv(z) = P~_cv(M_h^-T z) with M_h^-T = M_{h^-1}^T.  Frames as for
+// k_logsp_check; LDS per wavefront 2 kmax Q floats.
+template <int LOGQ>
+__global__ __launch_bounds__(64) void k_fsp_check(DevCode cd, int nf, const int* __restrict__ alist, int kmax,
+                                                  const float* __restrict__ v2c, float* __restrict__ c2v) {
+  using G = LsGeo<LOGQ>;
+  extern __shared__ float ls[];
+  float* in = ls;                // [kmax][Q] check coordinates
+  float* out = ls + kmax * G::Q; // [kmax][Q] extrinsic products, check coordinates
+  const int lane = threadIdx.x;
+  const long items = (long)nf * cd.M;
+  for (long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int fi = (int)(it / cd.M), c = (int)(it % cd.M);
+    const int f = alist ? alist[fi] : fi;
+    const int e0 = cd.row_ptr[c], deg = cd.row_ptr[c + 1] - e0;
+    for (int j = 0; j < deg; ++j) {
+      const int e = e0 + j;
+      const uint64_t cm = cd.colsT[cd.e_label[e]];
+      const float* src = v2c + ((size_t)f * cd.E + e) * G::Q;
+#pragma unroll
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int z = lane + 64 * xj;
+        if (z < G::Q) in[j * G::Q + z] = src[apply_mt<LOGQ>(cm, z)];
+      }
+    }
+    // each lane owns its z in both arrays: no barrier between the passes
+#pragma unroll
+    for (int xj = 0; xj < G::X; ++xj) {
+      const int z = lane + 64 * xj;
+      if (z < G::Q) {
+        float pre = 1.0f;
+        for (int j = 0; j < deg; ++j) {
+          out[j * G::Q + z] = pre;
+          pre *= in[j * G::Q + z];
+        }
+        float suf = 1.0f;
+        for (int j = deg - 1; j >= 0; --j) {
+          out[j * G::Q + z] *= suf;
+          suf *= in[j * G::Q + z];
+        }
+      }
+    }
+    __syncthreads();
+    for (int j = 0; j < deg; ++j) {
+      const int e = e0 + j;
+      const uint64_t cmi = cd.colsT[cd.ginv[cd.e_label[e]]];
+      float* dst = c2v + ((size_t)f * cd.E + e) * G::Q;
+#pragma unroll
+      for (int xj = 0; xj < G::X; ++xj) {
+        const int z = lane + 64 * xj;
+        if (z < G::Q) dst[z] = out[j * G::Q + apply_mt<LOGQ>(cmi, z)];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Low-bit message storage, emulated in place on FP32 message arrays: every
+// stored word is replaced by the nearest word of a b-bit format.
+//   kind 0 (Log-Fourier words, sign | -log2|P|): the sign and a (b-1)-bit
+//     unsigned magnitude on the grid {0, step, ..., (2^(b-1) - 1) step}
+//     (round to nearest, saturating);
+//   kind 1 (linear Fourier values P in [-1, 1]): b-bit two's complement
+//     fixed point with step 2^-(b-1) (round to nearest, saturating at
+//     +-(1 - 2^-(b-1)) and -1);
+//   kind 2 (Log-SP log2 pmfs, <= 0): b-bit unsigned -k * step, k = 0 ..
+//     2^b - 1 (round to nearest, saturating).
+__global__ void k_quantise(float* __restrict__ w, size_t n, int kind, int bits, float step) {
+  const float top = (float)((1 << (bits - 1)) - 1);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float x = w[i];
+    if (kind == 0) {
+      const float k = __builtin_fminf(__builtin_rintf(__builtin_fabsf(x) / step), top);
+      w[i] = __builtin_copysignf(k * step, x);
+    } else if (kind == 2) {
+      const float k = __builtin_fminf(__builtin_rintf(-x / step), (float)((1 << bits) - 1));
+      w[i] = -k * step;
+    } else {
+      const float sc = (float)(1 << (bits - 1));
+      const float k = __builtin_fminf(__builtin_fmaxf(__builtin_rintf(x * sc), -sc), top);
+      w[i] = k / sc;
+    }
   }
 }
 

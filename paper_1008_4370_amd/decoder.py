@@ -18,10 +18,11 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "ldpc_fd.h")
 
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP = 0, -1, -2, -3, -4
 PREC = {"fp32": 0, "fp16": 1, "bf16": 2}
-MODE = {"plain": 0, "fused": 1, "logsp": 2}
+MODE = {"plain": 0, "fused": 1, "logsp": 2, "fsp": 3}
 STATUS_CONVERGED, STATUS_MISMATCH = 1, 2
 K_FUSED, K_CHECK, K_VAR = 0, 1, 2
-TUNE = {"lane_entries": 0, "grid_blocks": 1, "chunk": 2, "graphs": 3, "tail_entries": 4, "tail_frames": 5, "precise": 6, "decision_mfma": 7, "tail_split": 8}
+TUNE = {"lane_entries": 0, "grid_blocks": 1, "chunk": 2, "graphs": 3, "tail_entries": 4, "tail_frames": 5, "precise": 6, "decision_mfma": 7, "tail_split": 8,
+        "quant_bits": 9, "quant_step": 10}
 
 _lib = None
 _c_void_p, _i32, _i64, _u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
@@ -233,7 +234,7 @@ def round_step(code: Code, llr, c2v_in=None, mode: str = "plain", prec: str = "f
     F = llr.shape[0]
     dev = llr.device
     c2v_out = torch.empty((F, code.E, code.q), dtype=torch.float32, device=dev)
-    v2c_out = torch.empty_like(c2v_out) if mode in ("plain", "logsp") else None
+    v2c_out = torch.empty_like(c2v_out) if mode != "fused" else None
     hard = torch.zeros((F, code.N), dtype=torch.uint8, device=dev)
     fsynd = torch.zeros((F, code.M), dtype=torch.uint8, device=dev)
     synd = torch.zeros((F, code.M), dtype=torch.uint8, device=dev)

@@ -35,7 +35,8 @@ def wilson(k: int, n: int, z: float = 1.96):
 
 def fer_curve(workload: str = "gf64_n1000", prec: str = "fp32", points=None, max_errors: int = 100,
               max_frames: int = 1 << 20, batch: int = 4096, max_iter: int = 100, seed: int = 77,
-              precise: bool = False, log=None) -> list[dict]:
+              precise: bool = False, log=None, mode: str = "fused", quant_bits: int = 0,
+              quant_step: int = 256) -> list[dict]:
     import torch
     w = synth.WORKLOADS[workload]
     b0 = synth.make_batch(workload, frames=batch)
@@ -46,8 +47,8 @@ def fer_curve(workload: str = "gf64_n1000", prec: str = "fp32", points=None, max
         autotune.apply(gcode, prec, batch)
     except Exception:
         pass
-    gcode.set_tuning(precise=1 if precise else 0)
-    dec = D.Decoder(gcode, batch, prec, "fused")
+    gcode.set_tuning(precise=1 if precise else 0, quant_bits=quant_bits, quant_step=quant_step)
+    dec = D.Decoder(gcode, batch, prec, mode)
     m = code.m
     cw = torch.from_numpy(b0.cw.astype(np.int64)).cuda()
     bits = ((cw[..., None] >> torch.arange(m, device="cuda")) & 1).float()
@@ -72,7 +73,8 @@ def fer_curve(workload: str = "gf64_n1000", prec: str = "fp32", points=None, max
             iters_sum += int(r["iters"].sum())
             frames += batch
         lo, hi = wilson(errors, frames)
-        res = {"ebn0": e, "prec": prec, "precise": precise, "frames": frames, "errors": errors, "fer": errors / frames,
+        res = {"ebn0": e, "prec": prec, "precise": precise, "mode": mode, "quant_bits": quant_bits,
+               "quant_step": quant_step / 4096, "frames": frames, "errors": errors, "fer": errors / frames,
                "fer_ci95": [lo, hi], "ber": bit_errors / (frames * code.N * m), "mean_iters": iters_sum / frames,
                "seconds": round(time.perf_counter() - t0, 2)}
         out.append(res)
@@ -109,9 +111,14 @@ if __name__ == "__main__":
     ap.add_argument("--max-errors", type=int, default=100)
     ap.add_argument("--max-frames", type=int, default=1 << 20)
     ap.add_argument("--target-fer", type=float, default=1e-2)
+    ap.add_argument("--mode", default="fused", choices=["fused", "plain", "logsp", "fsp"])
+    ap.add_argument("--quant-bits", type=int, default=0, help="emulated b-bit messages (PLAIN, FSP)")
+    ap.add_argument("--quant-step", type=int, default=256, help="Log-Fourier magnitude step in units of 2^-12")
+    ap.add_argument("--batch", type=int, default=4096)
     a = ap.parse_args()
-    curves = {p: fer_curve(a.workload, p.split("+")[0], a.points, a.max_errors, a.max_frames,
-                           precise=p.endswith("+p"), log=print) for p in a.prec}
+    curves = {p: fer_curve(a.workload, p.split("+")[0], a.points, a.max_errors, a.max_frames, batch=a.batch,
+                           precise=p.endswith("+p"), log=print, mode=a.mode, quant_bits=a.quant_bits,
+                           quant_step=a.quant_step) for p in a.prec}
     ref = a.prec[0]
     for p in a.prec[1:]:
         print(json.dumps({"gap_db": gap_db(curves[ref], curves[p], a.target_fer), "ref": ref, "prec": p,
