@@ -313,6 +313,28 @@ def main():
         code.set_tuning(**before)
         del pdec
 
+    prob_line = None
+    if args.mode == "fused" and not args.precise and not args.no_precise_variant:
+        # The same batch with the FP32 butterfly variable node (tuning key
+        # PRECISE = 0: prior convolution as m butterflies with tanh(L/2)
+        # factors); same tuned launch choices as the headline.
+        before = code.get_tuning()
+        code.set_tuning(precise=0)
+        qdec = D.Decoder(code, F, args.prec, args.mode)
+        qdec(llr, args.max_iter)
+        torch.cuda.synchronize()
+        tq0 = time.perf_counter()
+        for _ in range(args.steps):
+            qout = qdec(llr, args.max_iter)
+        torch.cuda.synchronize()
+        qms = (time.perf_counter() - tq0) / args.steps * 1e3
+        qhard = qout["hard"].cpu().numpy()
+        prob_line = {"ms_per_step": round(qms, 4),
+                     "value": round(F * batch.info_bits_per_frame / (qms / 1e3) / 1e6, 3),
+                     "fer": float(np.any(qhard != batch.cw, axis=1).mean())}
+        code.set_tuning(**before)
+        del qdec
+
     logsp_line = None
     if args.mode == "fused" and args.prec == "fp32" and not args.no_logsp_variant:
         # The same batch through the conventional log-domain SP decoder (the
@@ -430,6 +452,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "precise_variant": precise_line,
+        "butterfly_variant": prob_line,
         "logsp_variant": logsp_line,
         "fer": float(frame_err.mean()),
         "ber": bit_err / (F * batch.code.N * batch.code.m),

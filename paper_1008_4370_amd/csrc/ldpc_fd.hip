@@ -50,8 +50,10 @@ struct ldpc_fd_code_s {
   int tail_logr = 2, tail_frames = 128;
   // 1: such chunks run the edge-parallel pass (k_fused_split)
   int split = 1;
-  // 1: the fused pass evaluates the variable node in FP64 (see conv_prior_d)
-  int precise = 0;
+  // variable-node form of the fused pass (tuning key PRECISE): 0 = FP32 prior
+  // butterflies, 1 = FP64 (see conv_prior_d), 2 = FP32 through the
+  // convolution theorem with the channel pmf (conv_symbol_prior, prob_prior)
+  int precise = 2;
   // 1: the tentative decision's transforms on the matrix cores (FP16 MFMA,
   // variants with 16 frames per wavefront)
   int mfma = 0;
@@ -140,7 +142,8 @@ struct Impl {
   }
   // Edge-parallel pass (k_fused_split) over at most Fmax active frames: one
   // workgroup of KMAX wavefronts per (frame group, check), grid-stride.
-  // ar: arithmetic form of the variable node (kFp32, kFp64, kSymbolPrior).
+  // ar: arithmetic form of the variable node (kFp32, kFp64, kSymbolPrior,
+  // kProbPrior).
   template <typename S>
   static void fused_split(const DevCode& cd, int Fmax, const float* prior, S* buf0, S* buf1, uint8_t* hard,
                           uint8_t* fsw, const int* alist, const int* nact, const int* rnd, const int* maxit,
@@ -149,14 +152,20 @@ struct Impl {
     const long items = (long)((Fmax + G::T - 1) / G::T) * cd.M;
     const dim3 grid((unsigned)std::min<long>(items, 65536)), block(64 * KMAX);
     const size_t lds_bytes = (size_t)2 * KMAX * G::T * G::QP * sizeof(float);
-    // built forms: FP64 variable node with FP32/FP16 storage, symbol priors with
-    // FP32 storage (the entry points reject the other combinations)
+    // built forms: FP64 variable node with FP32/FP16 storage, symbol priors
+    // with FP32 storage (the entry points reject the other combinations); the
+    // FP32 forms with every storage type
     if constexpr (!std::is_same_v<S, bf16_t>) {
       if (ar == kFp64) {
         hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kFp64>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
                            fsw, alist, nact, rnd, maxit, maxit_all);
         return;
       }
+    }
+    if (ar == kProbPrior) {
+      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kProbPrior>), grid, block, lds_bytes, s, cd, prior, buf0, buf1,
+                         hard, fsw, alist, nact, rnd, maxit, maxit_all);
+      return;
     }
     if constexpr (std::is_same_v<S, float>) {
       if (ar == kSymbolPrior) {
@@ -187,6 +196,11 @@ struct Impl {
                            fsw, alist, nact, rnd, maxit, maxit_all);
         return;
       }
+    }
+    if (ar == kProbPrior) {
+      hipLaunchKernelGGL((k_fused<G, KMAX, S, kProbPrior, false>), grid, block, lds(), s, cd, prior, buf0, buf1,
+                         hard, fsw, alist, nact, rnd, maxit, maxit_all);
+      return;
     }
     if constexpr (std::is_same_v<S, float>) {
       if (ar == kSymbolPrior) {
@@ -301,6 +315,9 @@ bool dispatch(int m, int kmax, int logr, Fn&& fn) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Arithmetic form of the fused variable node for the PRECISE tuning value.
+int var_form(int precise) { return precise == 1 ? kFp64 : precise == 2 ? kProbPrior : kFp32; }
 
 size_t msg_bytes(int prec) { return prec == LDPC_FD_FP32 ? 4 : 2; }
 
@@ -625,7 +642,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   if (mode == LDPC_FD_MODE_FUSED && !c->regular)
     return fail(LDPC_FD_E_UNSUPPORTED, "the FUSED decoder needs column weight 2 (PLAIN and LOGSP take any)");
   if (prior && prec != LDPC_FD_FP32) return fail(LDPC_FD_E_UNSUPPORTED, "symbol priors need FP32 storage");
-  if (!prior && c->precise && prec == LDPC_FD_BF16 && mode == LDPC_FD_MODE_FUSED)
+  if (!prior && c->precise == 1 && prec == LDPC_FD_BF16 && mode == LDPC_FD_MODE_FUSED)
     return fail(LDPC_FD_E_UNSUPPORTED, "the FP64 variable node needs FP32 or FP16 storage");
   int64_t need = 0;
   int32_t rc = ldpc_fd_workspace_bytes(c, F, prec, mode, &need);
@@ -764,7 +781,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     tp = prior;
   else
     launch_prior(c, F, llr, w.prior, s);
-  const int ar = prior ? kSymbolPrior : c->precise ? kFp64 : kFp32;
+  const int ar = prior ? kSymbolPrior : var_form(c->precise);
   // One pass over the active frames (each at its own round, see k_fused),
   // syndromes of the decisions it formed, stopping rule and compaction.
   auto enqueue_round = [&](hipStream_t st, hipEvent_t e0, hipEvent_t e1, int lr, bool tail) {
@@ -911,7 +928,7 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   if (mode == LDPC_FD_MODE_FUSED && v2c_out) return fail(LDPC_FD_E_INVALID, "FUSED round does not form v2c_out");
   if (mode == LDPC_FD_MODE_FUSED && !c->regular)
     return fail(LDPC_FD_E_UNSUPPORTED, "the FUSED decoder needs column weight 2 (PLAIN and LOGSP take any)");
-  if (mode == LDPC_FD_MODE_FUSED && c->precise && prec == LDPC_FD_BF16)
+  if (mode == LDPC_FD_MODE_FUSED && c->precise == 1 && prec == LDPC_FD_BF16)
     return fail(LDPC_FD_E_UNSUPPORTED, "the FP64 variable node needs FP32 or FP16 storage");
   if (mode < LDPC_FD_MODE_PLAIN || mode > LDPC_FD_MODE_FSP) return fail(LDPC_FD_E_INVALID, "unknown mode");
   if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
@@ -982,9 +999,9 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
           if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, in, n_msg / 4);
         }
         if (c2v_in)
-          I::template fused<S>(cd, F, prior, out, in, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise ? kFp64 : kFp32, c->mfma, s);
+          I::template fused<S>(cd, F, prior, out, in, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, var_form(c->precise), c->mfma, s);
         else
-          I::template fused<S>(cd, F, prior, nullptr, out, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, c->precise ? kFp64 : kFp32, c->mfma, s);
+          I::template fused<S>(cd, F, prior, nullptr, out, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, var_form(c->precise), c->mfma, s);
         if (prec != LDPC_FD_FP32)
           hipLaunchKernelGGL((k_convert<S, float>), dim3(g), dim3(256), 0, s, (const S*)out, c2v_out, n_msg / 4);
       };
@@ -1038,7 +1055,7 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
       c->tail_frames = value;
       return LDPC_FD_OK;
     case LDPC_FD_TUNE_PRECISE:
-      if (value != 0 && value != 1) return fail(LDPC_FD_E_INVALID, "precise: 0 or 1");
+      if (value < 0 || value > 2) return fail(LDPC_FD_E_INVALID, "precise: 0, 1 or 2");
       c->precise = value;
       return LDPC_FD_OK;
     case LDPC_FD_TUNE_DECISION_MFMA:

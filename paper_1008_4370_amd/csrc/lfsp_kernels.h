@@ -381,8 +381,9 @@ struct EdgeLoads {
 };
 
 // Arithmetic forms of the variable node: BPSK prior factors in FP32 or FP64,
-// or a symbol prior pmf per variable (FP32).
-constexpr int kFp32 = 0, kFp64 = 1, kSymbolPrior = 2;
+// a symbol prior pmf per variable (FP32), or the BPSK prior as a pmf formed
+// from its bit probabilities (FP32, kProbPrior).
+constexpr int kFp32 = 0, kFp64 = 1, kSymbolPrior = 2, kProbPrior = 3;
 
 template <class G, typename S, int AR>
 __device__ __forceinline__ void issue_edge(const DevCode& cd, const float* __restrict__ tp, const S* __restrict__ cin,
@@ -405,16 +406,45 @@ __device__ __forceinline__ void issue_edge(const DevCode& cd, const float* __res
 // Pr(X_v = x | y_v) directly): Y = P0 (*) X is the transform of p0 . x, where x
 // is the inverse transform of X, so Y = WHT(p0 . WHT(X)) up to a positive
 // factor.  wht_s returns s(z) times the transform, s(z) = (-1)^popcount(zl)
-// constant per lane; multiplying by s after each transform removes it.
+// constant per lane; multiplying by s after each transform removes it.  x is a
+// pmf up to that factor, so its negative entries (rounding of near-certain
+// messages) are set to zero before the product: in FP32 this removes most of
+// the frame errors that the Fourier-domain form adds over the FP64 oracle.
 template <class G>
 __device__ __forceinline__ void conv_symbol_prior(float (&v)[G::R], const float (&pr)[G::R], int zl) {
   const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
   wht_s<G>(v, zl);
 #pragma unroll
-  for (int r = 0; r < G::R; ++r) v[r] *= sz * pr[r];
+  for (int r = 0; r < G::R; ++r) v[r] = __builtin_fmaxf(v[r] * sz, 0.0f) * pr[r];
   wht_s<G>(v, zl);
 #pragma unroll
   for (int r = 0; r < G::R; ++r) v[r] *= sz;
+}
+
+// The BPSK channel pmf p0(x) = prod_i Pr(b_i = x_i | y) of the lane's entries,
+// from the signed complements u_i = sign(L_i) (1 - |tanh(L_i / 2)|): the less
+// likely value of bit i has probability |u_i| / 2 = 1 / (1 + e^|L_i|), kept at
+// full relative precision, the likelier one 1 - |u_i| / 2.
+template <class G>
+__device__ __forceinline__ void prob_prior(const float (&u)[G::LOGQ], int zl, float (&pr)[G::R]) {
+  float p0[G::LOGQ], p1[G::LOGQ];
+#pragma unroll
+  for (int i = 0; i < G::LOGQ; ++i) {
+    const float a = 0.5f * __builtin_fabsf(u[i]);
+    const bool zero_likelier = !__builtin_signbit(u[i]);
+    p0[i] = zero_likelier ? 1.0f - a : a;
+    p1[i] = zero_likelier ? a : 1.0f - a;
+  }
+  // factors multiplied in bit order 0..m-1 for every geometry, so that every
+  // lane layout gives the same FP32 result
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) {
+    const int z = G::z_of(zl, r);
+    float v = 1.0f;
+#pragma unroll
+    for (int i = 0; i < G::LOGQ; ++i) v *= ((z >> i) & 1) ? p1[i] : p0[i];
+    pr[r] = v;
+  }
 }
 
 // P (precise): the variable node in FP64 (prior factors given as signed
@@ -453,7 +483,7 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
       const int h = uni(cd.e_label[e]);
       float t[G::LOGQ];
 #pragma unroll
-      for (int i = 0; i < G::LOGQ; ++i) t[i] = cur.l[i];   // prior factors (P: signed complements)
+      for (int i = 0; i < G::LOGQ; ++i) t[i] = cur.l[i];   // prior factors (P, kProbPrior: signed complements)
       double y64[P ? G::R : 1];
       if constexpr (P) {
 #pragma unroll
@@ -465,10 +495,15 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
 #pragma unroll
         for (int r = 0; r < G::R; ++r)
           st[j][r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
-        if constexpr (AR == kSymbolPrior)
+        if constexpr (AR == kSymbolPrior) {
           conv_symbol_prior<G>(st[j], cur.pr, zl);
-        else
+        } else if constexpr (AR == kProbPrior) {
+          float pr[G::R];
+          prob_prior<G>(t, zl, pr);
+          conv_symbol_prior<G>(st[j], pr, zl);
+        } else {
           conv_prior<G>(st[j], t);
+        }
       }
       if (any_decide && e < eo) {
         float xo[G::R];
@@ -619,10 +654,15 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
       } else {
 #pragma unroll
         for (int r = 0; r < G::R; ++r) st[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
-        if constexpr (AR == kSymbolPrior)
+        if constexpr (AR == kSymbolPrior) {
           conv_symbol_prior<G>(st, cur.pr, zl);
-        else
+        } else if constexpr (AR == kProbPrior) {
+          float pr[G::R];
+          prob_prior<G>(t, zl, pr);
+          conv_symbol_prior<G>(st, pr, zl);
+        } else {
           conv_prior<G>(st, t);
+        }
       }
       if (any_decide && e < eo) {
         float xo[G::R];

@@ -273,6 +273,86 @@ __device__ __forceinline__ void decide_wave(const DevCode& cd, const float (&lp)
   }
 }
 
+// Signs of the transform of the log2 posterior lp at e_i (bitwise-MAP symbol)
+// and at M_h^T e_i for two edges with label maps c1, c2 (colsT words).
+template <int LOGQ>
+__device__ __forceinline__ void decide_wave2(const float (&lp)[LsGeo<LOGQ>::X], uint64_t c1, uint64_t c2, int& hd,
+                                             int& w1, int& w2) {
+  using G = LsGeo<LOGQ>;
+  const int lane = lane_id();
+  const float mp = row_max<LOGQ>(lp);
+  float p[G::X];
+#pragma unroll
+  for (int xj = 0; xj < G::X; ++xj) {
+    const int x = lane + 64 * xj;
+    p[xj] = x < G::Q ? __builtin_amdgcn_exp2f(lp[xj] - mp) : 0.0f;
+  }
+  wave_wht<LOGQ>(p);
+  uint64_t neg[G::X];
+#pragma unroll
+  for (int xj = 0; xj < G::X; ++xj) neg[xj] = __ballot(p[xj] < 0.0f);
+  auto sign_at = [&](int z) {
+    uint64_t w = neg[0];
+#pragma unroll
+    for (int xj = 1; xj < G::X; ++xj)
+      if ((z >> 6) == xj) w = neg[xj];
+    return (int)((w >> (z & 63)) & 1);
+  };
+  hd = w1 = w2 = 0;
+#pragma unroll
+  for (int i = 0; i < LOGQ; ++i) {
+    hd |= sign_at(1 << i) << i;
+    w1 |= sign_at((int)((c1 >> (8 * i)) & 0xff)) << i;
+    w2 |= sign_at((int)((c2 >> (8 * i)) & 0xff)) << i;
+  }
+}
+
+// The Log-SP variable node of a weight-2 column, in registers: the message to
+// each check is the prior plus the other check's message.
+template <int LOGQ>
+__device__ __forceinline__ void logsp_var_w2(const DevCode& cd, int f, int v, int e1, int e2,
+                                             const float (&lp)[LsGeo<LOGQ>::X], const float* __restrict__ c2v,
+                                             float* __restrict__ v2c, uint8_t* __restrict__ hard,
+                                             uint8_t* __restrict__ fsw, int first) {
+  using G = LsGeo<LOGQ>;
+  const int lane = lane_id();
+  const uint64_t c1 = cd.colsT[cd.e_label[e1]], c2 = cd.colsT[cd.e_label[e2]];
+  const float* m1 = c2v + ((size_t)f * cd.E + e1) * G::Q;
+  const float* m2 = c2v + ((size_t)f * cd.E + e2) * G::Q;
+  float a1[G::X], a2[G::X], r1[G::X];
+#pragma unroll
+  for (int xj = 0; xj < G::X; ++xj) {
+    const int x = lane + 64 * xj;
+    a1[xj] = a2[xj] = lp[xj];
+    r1[xj] = 0.0f;
+    if (!first && x < G::Q) {
+      r1[xj] = m1[x];
+      a1[xj] += m2[x];  // to the check of e1: the prior and the message from the check of e2
+      a2[xj] += r1[xj];
+    }
+  }
+  const float mx1 = row_max<LOGQ>(a1), mx2 = row_max<LOGQ>(a2);
+#pragma unroll
+  for (int xj = 0; xj < G::X; ++xj) {
+    const int x = lane + 64 * xj;
+    if (x < G::Q) {
+      v2c[((size_t)f * cd.E + e1) * G::Q + x] = __builtin_fmaxf(a1[xj] - mx1, -kLsFloor);
+      v2c[((size_t)f * cd.E + e2) * G::Q + x] = __builtin_fmaxf(a2[xj] - mx2, -kLsFloor);
+    }
+  }
+  if (first) return;
+  float post[G::X];
+#pragma unroll
+  for (int xj = 0; xj < G::X; ++xj) post[xj] = a1[xj] + r1[xj];
+  int hd, w1, w2;
+  decide_wave2<LOGQ>(post, c1, c2, hd, w1, w2);
+  if (lane == 0) {
+    hard[(size_t)f * cd.N + v] = (uint8_t)hd;
+    fsw[(size_t)f * cd.E + e1] = (uint8_t)w1;
+    fsw[(size_t)f * cd.E + e2] = (uint8_t)w2;
+  }
+}
+
 // VARIABLE TO CHECK and TENTATIVE DECISION (Sec. 2.2) of the Log-SP decoder,
 // any column weight j <= 16, for the frames listed as for the check node.
 // With first != 0 the message to each check is the prior (round 0, no
@@ -295,6 +375,10 @@ __global__ __launch_bounds__(64) void k_logsp_var(DevCode cd, int nf, const int*
     const int eb = cd.v_ptr[v], ee = cd.v_ptr[v + 1];
     float lp[G::X];
     log_prior<LOGQ>(llr + ((size_t)f * cd.N + v) * LOGQ, lp);
+    if (ee - eb == 2) {  // the (2,k) codes: registers only
+      logsp_var_w2<LOGQ>(cd, f, v, cd.v_list[eb], cd.v_list[eb + 1], lp, c2v, v2c, hard, fsw, first);
+      continue;
+    }
     if (first) {
       const float mx = row_max<LOGQ>(lp);
       for (int k = eb; k < ee; ++k) {

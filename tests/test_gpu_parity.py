@@ -46,7 +46,7 @@ def _dev(x, dtype=None):
     return t.cuda()
 
 
-@pytest.mark.parametrize("mode", ["plain", "fused", "fused+precise"])
+@pytest.mark.parametrize("mode", ["plain", "fused", "fused+precise", "fused+butterfly"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_one_round_message_parity(case, mode):
     """From the same imported state, one GPU round matches the oracle's round:
@@ -56,8 +56,8 @@ def test_one_round_message_parity(case, mode):
     code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0)
     print(f"[case] {name} mode={mode} F={F}", flush=True)
     gcode = D.Code.from_synth(code)
-    if mode == "fused+precise":
-        gcode.set_tuning(precise=1)
+    if mode in ("fused+precise", "fused+butterfly"):
+        gcode.set_tuning(precise=1 if mode == "fused+precise" else 0)
         mode = "fused"
     L = _dev(llr)
     c2vs, v2cs, decs = run_rounds(tc, llr.astype(np.float64), 3)
@@ -100,7 +100,11 @@ def test_one_round_message_parity(case, mode):
 # arithmetic on identical inputs.  The test therefore bounds the 99.9th
 # percentile of the entry-wise difference (a broken storage path moves most
 # entries by 0.1-1) and prints the maximum and the storage error against the
-# unrounded oracle.
+# unrounded oracle.  The variable node runs in the butterfly form (PRECISE =
+# 0), whose arithmetic is the oracle's on any input: a rounded state is not the
+# transform of a nonnegative vector, and the default form's clamping of the
+# message pmf at zero (a projection the oracle does not make) would add its own
+# difference on exactly those inputs.
 STORAGE_TOL = {"fp16": 1e-3, "bf16": 1e-2}
 
 
@@ -110,6 +114,7 @@ def test_one_round_storage_parity(case, prec):
     name, m, k, N, F, ebn0 = case
     code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0)
     gcode = D.Code.from_synth(code)
+    gcode.set_tuning(precise=0)
     L = _dev(llr)
     ll = llr.astype(np.float64)
     c2vs, _, _ = run_rounds(tc, ll, 3)
@@ -302,13 +307,14 @@ def test_precise_variable_node_when_channel_and_messages_disagree():
     well = np.abs(oracle_round(bumped) - ref) < 1e-6
     gcode = D.Code.from_synth(code)
     errs = {}
-    for precise in (0, 1):
+    for precise in (0, 1, 2):
         gcode.set_tuning(precise=precise)
         out = D.round_step(gcode, _dev(llr2), _dev(words), "fused")
         torch.cuda.synchronize()
         errs[precise] = float(np.abs(from_state(out["c2v"].cpu().numpy()) - ref)[well].max())
     print(f"  {well.mean():.1%} of entries well-conditioned; one-round max |dP| on them: "
-          f"FP32 variable node {errs[0]:.2e}, FP64 variable node {errs[1]:.2e}", flush=True)
+          f"FP32 variable node {errs[0]:.2e}, FP64 variable node {errs[1]:.2e}, "
+          f"FP32 probability-domain prior {errs[2]:.2e}", flush=True)
     assert well.mean() > 0.9
     assert errs[1] < TOL_FP32
     assert errs[1] <= errs[0]
@@ -328,7 +334,7 @@ def test_decision_on_matrix_cores(case):
     print(f"[case] mfma decision {name} F={F}", flush=True)
     code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0)
     gcode = D.Code.from_synth(code)
-    gcode.set_tuning(lane_entries=(1 << m) // 4)
+    gcode.set_tuning(lane_entries=(1 << m) // 4, precise=0)   # MFMA decision: butterfly form
     L = _dev(llr)
     c2vs, _, decs = run_rounds(tc, llr.astype(np.float64), 3)
     for i in (0, 1):
@@ -354,7 +360,7 @@ def test_decision_on_matrix_cores_full_decode():
     name, m, k, N, F, ebn0 = CASES[5]
     code, enc, cw, llr, tc = _setup(m, k, N, 256, ebn0)
     gcode = D.Code.from_synth(code)
-    gcode.set_tuning(lane_entries=16)
+    gcode.set_tuning(lane_entries=16, precise=0)   # MFMA decision: butterfly form
     L = _dev(llr)
     res = []
     for mf in (0, 1):
@@ -368,7 +374,7 @@ def test_decision_on_matrix_cores_full_decode():
 
 
 @pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[5], CASES[8]], ids=lambda c: c[0])
-@pytest.mark.parametrize("precise", [0, 1])
+@pytest.mark.parametrize("precise", [0, 1, 2])
 def test_edge_parallel_tail_pass_is_identical(case, precise):
     """Chunks with few active frames run the edge-parallel pass (one wavefront
     per edge); it sums a check's magnitudes in the same order as the
@@ -434,17 +440,49 @@ def test_symbol_prior_decoding(case):
 
 def test_unbuilt_combinations_are_rejected():
     """The FP64 variable node with BF16 storage and symbol priors with 16-bit
-    storage are not built: the entry points return E_UNSUPPORTED."""
+    storage are not built: the entry points return E_UNSUPPORTED (the FP32
+    forms take every storage type)."""
     code, enc, cw, llr, tc = _setup(6, 6, 60, 4, 2.5)
     gcode = D.Code.from_synth(code)
     gcode.set_tuning(precise=1)
     with pytest.raises(D.LdpcFdError) as ei:
         D.decode(gcode, _dev(llr), 10, prec="bf16", mode="fused")
     assert ei.value.rc == -2
-    gcode.set_tuning(precise=0)
+    gcode.set_tuning(precise=2)
     dec = D.Decoder(gcode, 4, "fp16", "fused")
     p0 = channel_prior(llr.astype(np.float64), 6).astype(np.float32)
     with pytest.raises(D.LdpcFdError) as ei:
         dec.decode_prior(_dev(p0), 10)
     assert ei.value.rc == -2
     gcode.close()
+
+
+def test_probability_domain_prior_decodes_like_the_oracle():
+    """GF(64) (2,6) N=1000, 4096 frames at 2.5 dB: the FP32 variable node through
+    the convolution theorem with a clamped message pmf (PRECISE = 2, the
+    default) fails on fewer than half as many frames as the FP32 butterfly form
+    (PRECISE = 0), its outputs are
+    self-consistent, and the frames the butterfly form fails are decoded as the
+    FP64 oracle decodes them on most (>= 70%) of those frames (the oracle
+    itself decodes all but one of them)."""
+    b = synth.make_batch("gf64_n1000", point=2)
+    print("[case] gf64_n1000 full precise=2", flush=True)
+    gcode = D.Code.from_synth(b.code)
+    L = _dev(b.llr)
+    gcode.set_tuning(precise=0)
+    base = {k: v.cpu().numpy() for k, v in D.decode(gcode, L, 100).items()}
+    gcode.set_tuning(precise=2)
+    out = {k: v.cpu().numpy() for k, v in D.decode(gcode, L, 100).items()}
+    gcode.close()
+    _check_outputs(out, b.enc, 100)
+    fer0 = np.any(base["hard"] != b.cw, axis=1).mean()
+    fer2 = np.any(out["hard"] != b.cw, axis=1).mean()
+    print(f"[prob prior] FER butterfly form {fer0:.5f} -> {fer2:.5f}", flush=True)
+    assert fer2 < 0.5 * fer0
+    bad = np.nonzero(np.any(base["hard"] != b.cw, axis=1))[0][:16]
+    tc = TannerCode(b.code.M, b.code.N, b.code.m, b.code.row_ptr, b.code.col, b.code.val, b.code.poly)
+    ref = odecode(tc, b.llr[bad], 100)
+    agree = np.all(out["hard"][bad] == ref.hard, axis=1)
+    print(f"[prob prior] on {len(bad)} frames the butterfly form fails: equal to the oracle {agree.mean():.3f}",
+          flush=True)
+    assert agree.mean() >= 0.7
