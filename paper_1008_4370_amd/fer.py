@@ -35,7 +35,7 @@ def wilson(k: int, n: int, z: float = 1.96):
 
 def fer_curve(workload: str = "gf64_n1000", prec: str = "fp32", points=None, max_errors: int = 100,
               max_frames: int = 1 << 20, batch: int = 4096, max_iter: int = 100, seed: int = 77,
-              precise: bool = False, log=None, mode: str = "fused", quant_bits: int = 0,
+              precise: int | None = None, log=None, mode: str = "fused", quant_bits: int = 0,
               quant_step: int = 256) -> list[dict]:
     import torch
     w = synth.WORKLOADS[workload]
@@ -47,7 +47,9 @@ def fer_curve(workload: str = "gf64_n1000", prec: str = "fp32", points=None, max
         autotune.apply(gcode, prec, batch)
     except Exception:
         pass
-    gcode.set_tuning(precise=1 if precise else 0, quant_bits=quant_bits, quant_step=quant_step)
+    if precise is not None:   # None: the library's default variable-node form
+        gcode.set_tuning(precise=int(precise))
+    gcode.set_tuning(quant_bits=quant_bits, quant_step=quant_step)
     dec = D.Decoder(gcode, batch, prec, mode)
     m = code.m
     cw = torch.from_numpy(b0.cw.astype(np.int64)).cuda()
@@ -73,7 +75,7 @@ def fer_curve(workload: str = "gf64_n1000", prec: str = "fp32", points=None, max
             iters_sum += int(r["iters"].sum())
             frames += batch
         lo, hi = wilson(errors, frames)
-        res = {"ebn0": e, "prec": prec, "precise": precise, "mode": mode, "quant_bits": quant_bits,
+        res = {"ebn0": e, "prec": prec, "precise": gcode.get_tuning()["precise"], "mode": mode, "quant_bits": quant_bits,
                "quant_step": quant_step / 4096, "frames": frames, "errors": errors, "fer": errors / frames,
                "fer_ci95": [lo, hi], "ber": bit_errors / (frames * code.N * m), "mean_iters": iters_sum / frames,
                "seconds": round(time.perf_counter() - t0, 2)}
@@ -106,7 +108,8 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser(description="FER curves of the GPU decoder per storage precision")
     ap.add_argument("--workload", default="gf64_n1000")
     ap.add_argument("--prec", nargs="+", default=["fp32", "fp16"],
-                    help="storage precisions; a '+p' suffix (fp32+p) selects the FP64 variable node")
+                    help="storage precisions; suffix '+p' (fp32+p) selects the FP64 variable node, '+b' the FP32 "
+                         "butterfly form; no suffix the library default")
     ap.add_argument("--points", type=float, nargs="*", default=None)
     ap.add_argument("--max-errors", type=int, default=100)
     ap.add_argument("--max-frames", type=int, default=1 << 20)
@@ -117,7 +120,8 @@ if __name__ == "__main__":
     ap.add_argument("--batch", type=int, default=4096)
     a = ap.parse_args()
     curves = {p: fer_curve(a.workload, p.split("+")[0], a.points, a.max_errors, a.max_frames, batch=a.batch,
-                           precise=p.endswith("+p"), log=print, mode=a.mode, quant_bits=a.quant_bits,
+                           precise={"p": 1, "b": 0}.get(p.split("+")[1]) if "+" in p else None, log=print,
+                           mode=a.mode, quant_bits=a.quant_bits,
                            quant_step=a.quant_step) for p in a.prec}
     ref = a.prec[0]
     for p in a.prec[1:]:
