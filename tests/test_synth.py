@@ -39,3 +39,26 @@ def test_channel_llr_statistics():
     s2 = synth.sigma2_from_ebn0(2.0, code.design_rate)
     assert abs(L.mean() - 2 / s2) < 0.02 * (2 / s2)
     assert abs(L.var() - 4 / s2) < 0.03 * (4 / s2)
+
+
+def test_irregular_column_weights():
+    """Column weights follow the requested fractions (rounding absorbed by the
+    largest), rows stay near-regular, no double edges, codewords exist."""
+    vd = synth.irregular_var_degrees(1000, {2: 0.7, 3: 0.2, 4: 0.1}, seed=3)
+    assert dict(zip(*np.unique(vd, return_counts=True))) == {2: 700, 3: 200, 4: 100}
+    c = synth.make_code(1000, 6, 6, var_degrees=vd)
+    assert np.array_equal(np.bincount(c.col, minlength=1000), vd)
+    d = np.diff(c.row_ptr)
+    assert c.M == round(vd.sum() / 6) and d.max() - d.min() <= 1 and d.sum() == vd.sum()
+    key = np.repeat(np.arange(c.M), d).astype(np.int64) * 1000 + c.col
+    assert len(np.unique(key)) == len(key)
+    vd1 = synth.irregular_var_degrees(64, {1: 0.05, 2: 0.6, 3: 0.25, 5: 0.1}, seed=44)
+    c1 = synth.make_code(64, 5, 4, var_degrees=vd1)
+    enc = synth.Encoder(c1)
+    assert np.all(enc.syndrome(synth.random_codewords(enc, 10)) == 0)
+
+
+def test_irregular_workload_batch():
+    b = synth.make_batch("gf64_n1000_irr", frames=4)
+    assert b.code.M == 400 and np.all(b.enc.syndrome(b.cw) == 0)
+    assert sorted(set(np.bincount(b.code.col, minlength=b.code.N))) == [2, 3, 4]
