@@ -56,17 +56,12 @@ __device__ __forceinline__ void prior_coeffs(const float* llr_fv, float (&t)[G::
 // the first two transforms cancel in the product; the third is undone with
 // s(z) before the values are written to the frame's LDS row, from which the
 // 3m points are read.
+// Signs of Q(z) = s(z) A(z) (A as wht_s returns it) at the 3m read points:
+// e_i (bitwise-MAP bits) and M_h^T e_i for the two edges of the variable
+// (cols_a, cols_b), read back through the frame's LDS row.
 template <class G>
-__device__ __forceinline__ void decide(const float (&Y)[G::R], float (&Xo)[G::R], float* lds, int rb, int cf,
-                                       int zl, uint64_t cols_a, uint64_t cols_b, int& hard, int& fa, int& fb) {
-  float A[G::R];
-#pragma unroll
-  for (int r = 0; r < G::R; ++r) A[r] = Y[r];
-  wht_s<G>(A, zl);
-  wht_s<G>(Xo, zl);
-#pragma unroll
-  for (int r = 0; r < G::R; ++r) A[r] *= Xo[r];
-  wht_s<G>(A, zl);
+__device__ __forceinline__ void decide_signs(float (&A)[G::R], float* lds, int rb, int cf, int zl, uint64_t cols_a,
+                                             uint64_t cols_b, int& hard, int& fa, int& fb) {
   const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
 #pragma unroll
   for (int r = 0; r < G::R; ++r) A[r] *= sz;
@@ -82,6 +77,36 @@ __device__ __forceinline__ void decide(const float (&Y)[G::R], float (&Xo)[G::R]
     fb |= (lds[rcf ^ (int)((cols_b >> (8 * i)) & 0xFF)] < 0.0f) << i;
   }
   __builtin_amdgcn_wave_barrier();
+}
+
+template <class G>
+__device__ __forceinline__ void decide(const float (&Y)[G::R], float (&Xo)[G::R], float* lds, int rb, int cf,
+                                       int zl, uint64_t cols_a, uint64_t cols_b, int& hard, int& fa, int& fb) {
+  float A[G::R];
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) A[r] = Y[r];
+  wht_s<G>(A, zl);
+  wht_s<G>(Xo, zl);
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) A[r] *= Xo[r];
+  wht_s<G>(A, zl);
+  decide_signs<G>(A, lds, rb, cf, zl, cols_a, cols_b, hard, fa, fb);
+}
+
+// The decision from the posterior pmf when the variable node already formed
+// pp = p0 . x_c' (the channel pmf times the other message's pmf, clamped):
+// the posterior pmf is pp . x_c with x_c the own message's pmf (inverse
+// transform of Xo, clamped at zero likewise), one transform back gives Q.
+// Two Hadamard transforms instead of three.  Xo is overwritten.
+template <class G>
+__device__ __forceinline__ void decide_pmf(const float (&pp)[G::R], float (&Xo)[G::R], float* lds, int rb, int cf,
+                                           int zl, uint64_t cols_a, uint64_t cols_b, int& hard, int& fa, int& fb) {
+  const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
+  wht_s<G>(Xo, zl);
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) Xo[r] = __builtin_fmaxf(Xo[r] * sz, 0.0f) * pp[r];
+  wht_s<G>(Xo, zl);
+  decide_signs<G>(Xo, lds, rb, cf, zl, cols_a, cols_b, hard, fa, fb);
 }
 
 // ---- tentative decision on the matrix cores ------------------------------------
@@ -410,15 +435,29 @@ __device__ __forceinline__ void issue_edge(const DevCode& cd, const float* __res
 // pmf up to that factor, so its negative entries (rounding of near-certain
 // messages) are set to zero before the product: in FP32 this removes most of
 // the frame errors that the Fourier-domain form adds over the FP64 oracle.
+// First half: v := p0 . max(x, 0), x the inverse transform of V (the product
+// pmf, up to a positive factor).
 template <class G>
-__device__ __forceinline__ void conv_symbol_prior(float (&v)[G::R], const float (&pr)[G::R], int zl) {
+__device__ __forceinline__ void symbol_prior_product(float (&v)[G::R], const float (&pr)[G::R], int zl) {
   const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
   wht_s<G>(v, zl);
 #pragma unroll
   for (int r = 0; r < G::R; ++r) v[r] = __builtin_fmaxf(v[r] * sz, 0.0f) * pr[r];
+}
+
+// Second half: back to the Fourier domain.
+template <class G>
+__device__ __forceinline__ void symbol_prior_back(float (&v)[G::R], int zl) {
+  const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
   wht_s<G>(v, zl);
 #pragma unroll
   for (int r = 0; r < G::R; ++r) v[r] *= sz;
+}
+
+template <class G>
+__device__ __forceinline__ void conv_symbol_prior(float (&v)[G::R], const float (&pr)[G::R], int zl) {
+  symbol_prior_product<G>(v, pr, zl);
+  symbol_prior_back<G>(v, zl);
 }
 
 // The BPSK channel pmf p0(x) = prod_i Pr(b_i = x_i | y) of the lane's entries,
@@ -500,12 +539,28 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
         } else if constexpr (AR == kProbPrior) {
           float pr[G::R];
           prob_prior<G>(t, zl, pr);
-          conv_symbol_prior<G>(st[j], pr, zl);
+          symbol_prior_product<G>(st[j], pr, zl);
+          // owner visit: the decision from the product pmf before the
+          // transform back (decide_pmf)
+          if (any_decide && e < eo) {
+            float xo[G::R];
+#pragma unroll
+            for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
+            int hd, fa, fo;
+            const int ho = uni(cd.e_label[eo]);
+            decide_pmf<G>(st[j], xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
+            if (valid && fs.decide && zl == 0) {
+              hard[(size_t)f * cd.N + v] = (uint8_t)hd;
+              fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
+              fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
+            }
+          }
+          symbol_prior_back<G>(st[j], zl);
         } else {
           conv_prior<G>(st[j], t);
         }
       }
-      if (any_decide && e < eo) {
+      if (AR != kProbPrior && any_decide && e < eo) {
         float xo[G::R];
 #pragma unroll
         for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
@@ -659,12 +714,26 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
         } else if constexpr (AR == kProbPrior) {
           float pr[G::R];
           prob_prior<G>(t, zl, pr);
-          conv_symbol_prior<G>(st, pr, zl);
+          symbol_prior_product<G>(st, pr, zl);
+          if (any_decide && e < eo) {
+            float xo[G::R];
+#pragma unroll
+            for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
+            int hd, fa, fo;
+            const int ho = uni(cd.e_label[eo]);
+            decide_pmf<G>(st, xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
+            if (valid && fs.decide && zl == 0) {
+              hard[(size_t)f * cd.N + v] = (uint8_t)hd;
+              fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
+              fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
+            }
+          }
+          symbol_prior_back<G>(st, zl);
         } else {
           conv_prior<G>(st, t);
         }
       }
-      if (any_decide && e < eo) {
+      if (AR != kProbPrior && any_decide && e < eo) {
         float xo[G::R];
 #pragma unroll
         for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
