@@ -23,7 +23,7 @@ struct LsGeo {
 
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
-  for (int s = 1; s < 64; s <<= 1) v = __builtin_fmaxf(v, __shfl_xor(v, s));
+  for (int s = 1; s < 64; s <<= 1) v = __builtin_fmaxf(v, lane_xor(v, s));
   return v;
 }
 
@@ -68,10 +68,10 @@ __device__ __forceinline__ void ls_conv(const float* f, const float* g, float* o
   }
 #pragma unroll
   for (int o = 1; o < S; o <<= 1) {
-    a0 += __shfl_xor(a0, o);
-    a1 += __shfl_xor(a1, o);
-    a2 += __shfl_xor(a2, o);
-    a3 += __shfl_xor(a3, o);
+    a0 += lane_xor(a0, o);
+    a1 += lane_xor(a1, o);
+    a2 += lane_xor(a2, o);
+    a3 += lane_xor(a3, o);
   }
   const float mx = __builtin_fmaxf(__builtin_fmaxf(a0, a1), __builtin_fmaxf(a2, a3));
   const float sc = __builtin_amdgcn_rcpf(wave_max(mx));
@@ -173,8 +173,9 @@ __global__ __launch_bounds__(64) void k_logsp_check(DevCode cd, int nf, const in
 // ---- wavefront-per-variable helpers (symbol x on lane x mod 64) -------------
 
 // Walsh-Hadamard transform of a length-Q vector held as p[j] = v(lane + 64 j):
-// butterflies over the in-register index, then over lanes.  Lanes >= Q (Q <
-// 64) must hold 0 and keep it.
+// butterflies over the in-register index, then over lanes (exchanges by DPP
+// for lane xor 1, 2, ds_swizzle for 4..16, ds_bpermute for 32; every lane of
+// the wavefront takes part).  Lanes >= Q (Q < 64) must hold 0 and keep it.
 template <int LOGQ>
 __device__ __forceinline__ void wave_wht(float (&p)[LsGeo<LOGQ>::X]) {
   using G = LsGeo<LOGQ>;
@@ -193,7 +194,7 @@ __device__ __forceinline__ void wave_wht(float (&p)[LsGeo<LOGQ>::X]) {
   for (int sh = 1; sh < (G::Q < 64 ? G::Q : 64); sh <<= 1) {
 #pragma unroll
     for (int xj = 0; xj < G::X; ++xj) {
-      const float o = __shfl_xor(p[xj], sh);
+      const float o = lane_xor(p[xj], sh);
       p[xj] = (lane & sh) ? o - p[xj] : p[xj] + o;
     }
   }
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(64) void k_var_gen(DevCode cd, int nf, const int* _
         a[xj] = x < G::Q ? __builtin_amdgcn_exp2f(a[xj] - mx) : 0.0f;
       }
       wave_wht<LOGQ>(a);
-      const float y0 = __builtin_fmaxf(__shfl(a[0], 0), 1e-37f);
+      const float y0 = __builtin_fmaxf(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(a[0]))), 1e-37f);
       const float lg0 = __builtin_amdgcn_logf(y0);
       const float r0 = 1.0f / y0;
       float* dst = v2c + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
