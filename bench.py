@@ -199,7 +199,8 @@ def main():
     ap.add_argument("--workload", default="gf64_n1000",
                     help="a synthetic workload name, or 'mixed' (three codes in one pool) or 'serving' "
                          "(Poisson arrivals over the three codes at several loads)")
-    ap.add_argument("--point", type=int, default=2, help="Eb/N0 index (gf64_n1000: 2 -> 2.5 dB)")
+    ap.add_argument("--point", type=int, default=None,
+                    help="Eb/N0 index into the workload's list (default: its 2.5 dB point, else its first)")
     ap.add_argument("--prec", default=None, choices=["fp32", "fp16", "bf16"],
                     help="message storage (default fp32; fp16 for the serving workload)")
     ap.add_argument("--mode", default="fused", choices=["fused", "plain"])
@@ -248,6 +249,9 @@ def main():
     if args.workload == "serving":
         return run_serving(args)
     from paper_1008_4370_amd import synth
+    if args.point is None:
+        pts = synth.WORKLOADS[args.workload]["ebn0"]
+        args.point = pts.index(2.5) if 2.5 in pts else 0
     batch = synth.make_batch(args.workload, point=args.point)
     F = batch.llr.shape[0]
     cpu = None
