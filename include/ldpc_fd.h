@@ -265,8 +265,9 @@ int32_t ldpc_fd_pool_submit(ldpc_fd_pool pool, int32_t code, const float *llr, i
 /* Enqueue `passes` (1..1000) passes over the active frames of every code: one
  * replay of a captured graph whose per-code branches run concurrently.  A code
  * whose admitted-but-unharvested frames number at most its tail threshold
- * (LDPC_FD_TUNE_TAIL_FRAMES) runs the few-frames form in this step; steps are
- * captured once per (passes, form per code) with the codes' tuning at that
+ * (LDPC_FD_TUNE_TAIL_FRAMES) runs the few-frames form in this step, and a code
+ * with none (every admitted frame harvested) is left out of the step; steps
+ * are captured once per (passes, form per code) with the codes' tuning at that
  * time.  Asynchronous.  Errors: E_INVALID, E_UNSUPPORTED, E_HIP. */
 int32_t ldpc_fd_pool_step(ldpc_fd_pool pool, int32_t passes);
 

@@ -191,26 +191,34 @@ def decode_mixed(pool: D.Pool, llrs, max_iter: int = 100, passes_per_step: int =
     """Decode one batch per pool code together: every frame is admitted at
     once (the pool needs as many slots as frames), each step replays one graph
     that runs `passes_per_step` passes of every code on concurrent streams,
-    and results are harvested when no frame is active.  Returns, per code,
-    dict(iters, status, hard) in frame order."""
+    and each code is harvested as soon as none of its frames is active (which
+    leaves it out of later steps).  Returns, per code, dict(iters, status,
+    hard) in frame order."""
     ncodes = len(llrs)
     for k, llr in enumerate(llrs):
         F = int(llr.shape[0])
         got = pool.submit(k, llr, np.arange(F, dtype=np.uint64), max_iter)
         if got != F:
             raise ValueError(f"pool code {k}: {F} frames but only {got} free slots")
-    for _ in range((max_iter + passes_per_step) // passes_per_step + 1):
-        pool.step(passes_per_step)
-        if all(pool.active(k) == 0 for k in range(ncodes)):
-            break
-    else:
-        raise RuntimeError("frames still active after max_iter + 1 passes")
-    out = []
-    for k, llr in enumerate(llrs):
-        F = int(llr.shape[0])
+    got = [None] * ncodes
+
+    def harvest(k):
+        F = int(llrs[k].shape[0])
         tags, it, st, hd = pool.harvest(k, F)
         if len(tags) != F:
             raise RuntimeError(f"pool code {k}: harvested {len(tags)} of {F} frames")
         order = np.argsort(tags)
-        out.append({"iters": it[order], "status": st[order], "hard": hd[order]})
-    return out
+        got[k] = {"iters": it[order], "status": st[order], "hard": hd[order]}
+
+    # a code whose frames have all stopped is harvested at once, which takes it
+    # out of the following steps
+    for _ in range((max_iter + passes_per_step) // passes_per_step + 1):
+        pool.step(passes_per_step)
+        for k in range(ncodes):
+            if got[k] is None and pool.active(k) == 0:
+                harvest(k)
+        if all(g is not None for g in got):
+            break
+    else:
+        raise RuntimeError("frames still active after max_iter + 1 passes")
+    return got
