@@ -21,7 +21,7 @@ Every step follows the paper's order and notation:
   Sec. 3.1, Eq. (5), repeated for the Log-Fourier SP in Sec. 3.2):
   q_v(x) = p_v^(0)(x) prod_{c in C_v} p_cv(x) (normalised);
   bit i of x^_v is 1 iff the marginal q_{v,i}(1) > q_{v,i}(0) (a tie gives 0,
-  the deterministic choice for the paper's "choose randomly");
+  a deterministic choice where the paper leaves ties to a random one);
   direct syndrome s_c = sum_{v in V_c} h_cv x^_v;
   Fourier syndrome bit i of check c = XOR over v in V_c of [Q_v(M_h^T e_i) < 0]
   with Q_v the Fourier transform of q_v and h = h_cv.

@@ -1,10 +1,10 @@
 // The conventional log-domain sum-product decoder (Sec. 2.2), built as the
 // comparison the paper makes against the Log-Fourier SP (Table 1): messages
 // are log2 pmfs in the probability domain, the check node forms each extrinsic
-// message as the (k-1)-fold XOR convolution of the other messages (the "(k-1)-
-// fold CONV x k" of Table 1, via forward and backward partial convolutions,
-// 3(k-2) pairwise convolutions of q^2 log-sum-exp terms each), and the
-// variable node adds log vectors ("2-term ADD x 2").  One wavefront per
+// message as the XOR convolution of the other k-1 messages (k such
+// convolutions per check in Table 1's count; here through forward and backward
+// partial convolutions, 3(k-2) pairwise convolutions of q^2 log-sum-exp terms
+// in all), and the variable node adds log vectors.  One wavefront per
 // (frame, node); symbol x of a vector lives on lane x mod 64 (q/64 symbols per
 // lane for q > 64; lanes >= q idle for q < 64).  Log values are clamped to
 // [-kLsFloor, 0] after normalisation to max 0.
