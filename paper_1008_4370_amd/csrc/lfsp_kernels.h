@@ -508,15 +508,23 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
   Acc smag[G::R];
 #pragma unroll
   for (int r = 0; r < G::R; ++r) smag[r] = 0;
-  // edge j+1's loads are in flight while edge j is computed
-  EdgeLoads<G, S> nxt;
-  issue_edge<G, S, AR>(cd, tp, cin, fb, f, e0, fs, any_decide, zl, nxt);
+  // edge j+1's loads are in flight while edge j is computed.  TWO: two load
+  // buffers indexed by the (unrolled, constant) parity of j, which saves the
+  // register copies of the one-buffer form (about 90 VALU moves per edge in
+  // the default arithmetic); used where the loop is unrolled whole and the
+  // kernel compiles without private-memory spills, the one-buffer form
+  // elsewhere.
+  constexpr bool TWO = KMAX <= 8 && AR == kProbPrior && (G::LOGQ <= 6 || G::LOGR <= 3) && !std::is_same<S, _Float16>::value;
+  EdgeLoads<G, S> eb[TWO ? 2 : 1];
+  issue_edge<G, S, AR>(cd, tp, cin, fb, f, e0, fs, any_decide, zl, eb[0]);
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j < deg) {
       const int e = e0 + j;
-      const EdgeLoads<G, S> cur = nxt;
-      if (j + 1 < deg) issue_edge<G, S, AR>(cd, tp, cin, fb, f, e + 1, fs, any_decide, zl, nxt);
+      const int bc = TWO ? (j & 1) : 0, bn = TWO ? ((j + 1) & 1) : 0;
+      const EdgeLoads<G, S> cur0 = eb[bc];
+      const EdgeLoads<G, S>& cur = TWO ? eb[bc] : cur0;
+      if (j + 1 < deg) issue_edge<G, S, AR>(cd, tp, cin, fb, f, e + 1, fs, any_decide, zl, eb[bn]);
       const int v = uni(cd.e_var[e]);
       const int eo = uni(cd.e_other[e]);
       const int h = uni(cd.e_label[e]);
