@@ -338,8 +338,17 @@ struct bf16_t {
 
 template <typename S>
 struct IO;
+// load_words4 / entry: four entries kept as loaded (32-bit words, 16-bit
+// types two to a word) and converted one at a time where they are used, with
+// the same conversion as load4; kWords4 words per four entries.
 template <>
 struct IO<float> {
+  static constexpr int kWords4 = 4;
+  static __device__ __forceinline__ void load_words4(const float* p, uint32_t* w) {
+    const uint4 x = *reinterpret_cast<const uint4*>(p);
+    w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
+  }
+  static __device__ __forceinline__ float entry(const uint32_t* w, int i) { return __uint_as_float(w[i]); }
   static __device__ __forceinline__ void load4(const float* p, float* o) {
     const float4 x = *reinterpret_cast<const float4*>(p);
     o[0] = x.x; o[1] = x.y; o[2] = x.z; o[3] = x.w;
@@ -357,6 +366,15 @@ constexpr float kHalfScale = 512.0f;
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 template <>
 struct IO<_Float16> {
+  static constexpr int kWords4 = 2;
+  static __device__ __forceinline__ void load_words4(const _Float16* p, uint32_t* w) {
+    const uint2 x = *reinterpret_cast<const uint2*>(p);
+    w[0] = x.x; w[1] = x.y;
+  }
+  static __device__ __forceinline__ float entry(const uint32_t* w, int i) {
+    const uint16_t b = (uint16_t)((i & 1) ? (w[i >> 1] >> 16) : (w[i >> 1] & 0xFFFFu));
+    return (float)__builtin_bit_cast(_Float16, b) * (1.0f / kHalfScale);
+  }
   static __device__ __forceinline__ void load4(const _Float16* p, float* o) {
     const half4_t x = *reinterpret_cast<const half4_t*>(p);
 #pragma unroll
@@ -375,6 +393,14 @@ __device__ __forceinline__ uint32_t f32_to_bf16_rne(float f) {
 }
 template <>
 struct IO<bf16_t> {
+  static constexpr int kWords4 = 2;
+  static __device__ __forceinline__ void load_words4(const bf16_t* p, uint32_t* w) {
+    const uint2 x = *reinterpret_cast<const uint2*>(p);
+    w[0] = x.x; w[1] = x.y;
+  }
+  static __device__ __forceinline__ float entry(const uint32_t* w, int i) {
+    return __uint_as_float((i & 1) ? (w[i >> 1] & 0xFFFF0000u) : (w[i >> 1] << 16));
+  }
   static __device__ __forceinline__ void load4(const bf16_t* p, float* o) {
     const uint2 x = *reinterpret_cast<const uint2*>(p);
     o[0] = __uint_as_float(x.x << 16); o[1] = __uint_as_float(x.x & 0xFFFF0000u);
@@ -394,6 +420,11 @@ template <class G, typename S>
 __device__ __forceinline__ void load_msg(const S* base, int zl, float (&v)[G::R]) {
 #pragma unroll
   for (int h = 0; h < G::R / 4; ++h) IO<S>::load4(base + 4 * zl + 4 * G::L * h, &v[4 * h]);
+}
+template <class G, typename S>
+__device__ __forceinline__ void load_msg_words(const S* base, int zl, uint32_t* w) {
+#pragma unroll
+  for (int h = 0; h < G::R / 4; ++h) IO<S>::load_words4(base + 4 * zl + 4 * G::L * h, w + IO<S>::kWords4 * h);
 }
 template <class G, typename S>
 __device__ __forceinline__ void store_msg(S* base, int zl, const float (&v)[G::R]) {

@@ -396,13 +396,34 @@ __device__ __forceinline__ FrameState frame_state(const int* __restrict__ rnd, c
 }
 
 // Loads of one edge: the other edge's message, the own message (owner visits
-// of a deciding pass) and the prior factors of the variable.
+// of a deciding pass) and the prior factors of the variable.  PACK: the two
+// messages stay in their storage format (16-bit types two entries to a
+// register) until an entry is used, which frees registers for 16-bit storage;
+// otherwise they are converted to FP32 as they are loaded.
+template <class G, typename S, bool PACK>
+struct EdgeLoads;
 template <class G, typename S>
-struct EdgeLoads {
-  float x[G::R];
-  float o[G::R];
+struct EdgeLoads<G, S, true> {
+  static constexpr int W = G::R / 4 * IO<S>::kWords4;
+  uint32_t xw[W];   // incoming message of the variable's other edge
+  uint32_t ow[W];   // the edge's own message (decision at the owner visit)
   float l[G::LOGQ];   // prior factors t_i = tanh(L_i / 2) of the variable
   float pr[G::R];     // symbol prior p_v^(0)(x) (arithmetic form kSymbolPrior)
+  __device__ __forceinline__ float x(int r) const { return IO<S>::entry(xw + IO<S>::kWords4 * (r >> 2), r & 3); }
+  __device__ __forceinline__ float o(int r) const { return IO<S>::entry(ow + IO<S>::kWords4 * (r >> 2), r & 3); }
+  __device__ __forceinline__ void load_x(const S* p, int zl) { load_msg_words<G, S>(p, zl, xw); }
+  __device__ __forceinline__ void load_o(const S* p, int zl) { load_msg_words<G, S>(p, zl, ow); }
+};
+template <class G, typename S>
+struct EdgeLoads<G, S, false> {
+  float xf[G::R];
+  float of[G::R];
+  float l[G::LOGQ];
+  float pr[G::R];
+  __device__ __forceinline__ float x(int r) const { return xf[r]; }
+  __device__ __forceinline__ float o(int r) const { return of[r]; }
+  __device__ __forceinline__ void load_x(const S* p, int zl) { load_msg<G, S>(p, zl, xf); }
+  __device__ __forceinline__ void load_o(const S* p, int zl) { load_msg<G, S>(p, zl, of); }
 };
 
 // Arithmetic forms of the variable node: BPSK prior factors in FP32 or FP64,
@@ -410,10 +431,10 @@ struct EdgeLoads {
 // from its bit probabilities (FP32, kProbPrior).
 constexpr int kFp32 = 0, kFp64 = 1, kSymbolPrior = 2, kProbPrior = 3;
 
-template <class G, typename S, int AR>
+template <class G, typename S, int AR, bool PACK>
 __device__ __forceinline__ void issue_edge(const DevCode& cd, const float* __restrict__ tp, const S* __restrict__ cin,
                                            size_t fb, int f, int e, const FrameState& fs, bool any_decide, int zl,
-                                           EdgeLoads<G, S>& L) {
+                                           EdgeLoads<G, S, PACK>& L) {
   const int v = uni(cd.e_var[e]);
   const int eo = uni(cd.e_other[e]);
   if constexpr (AR == kSymbolPrior) {
@@ -423,8 +444,8 @@ __device__ __forceinline__ void issue_edge(const DevCode& cd, const float* __res
 #pragma unroll
     for (int i = 0; i < G::LOGQ; ++i) L.l[i] = lp[i];
   }
-  if (!fs.first) load_msg<G, S>(cin + fb + (size_t)eo * G::Q, zl, L.x);
-  if (any_decide && e < eo && fs.decide) load_msg<G, S>(cin + fb + (size_t)e * G::Q, zl, L.o);
+  if (!fs.first) L.load_x(cin + fb + (size_t)eo * G::Q, zl);
+  if (any_decide && e < eo && fs.decide) L.load_o(cin + fb + (size_t)e * G::Q, zl);
 }
 
 // XOR convolution with a general symbol prior (Sec. 2.1: the channel gives
@@ -514,17 +535,20 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
   // the default arithmetic); used where the loop is unrolled whole and the
   // kernel compiles without private-memory spills, the one-buffer form
   // elsewhere.
-  constexpr bool TWO = KMAX <= 8 && AR == kProbPrior && (G::LOGQ <= 6 || G::LOGR <= 3) && !std::is_same<S, _Float16>::value;
-  EdgeLoads<G, S> eb[TWO ? 2 : 1];
-  issue_edge<G, S, AR>(cd, tp, cin, fb, f, e0, fs, any_decide, zl, eb[0]);
+  // Packed loads where the edge loop unrolls whole (KMAX <= 8); with 16
+  // edges the one-buffer, converted form keeps the loop as it compiles best.
+  constexpr bool TWO = KMAX <= 8 && AR == kProbPrior && (G::LOGQ <= 6 || G::LOGR <= 3);
+  constexpr bool PACK = KMAX <= 8;
+  EdgeLoads<G, S, PACK> eb[TWO ? 2 : 1];
+  issue_edge<G, S, AR, PACK>(cd, tp, cin, fb, f, e0, fs, any_decide, zl, eb[0]);
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j < deg) {
       const int e = e0 + j;
       const int bc = TWO ? (j & 1) : 0, bn = TWO ? ((j + 1) & 1) : 0;
-      const EdgeLoads<G, S> cur0 = eb[bc];
-      const EdgeLoads<G, S>& cur = TWO ? eb[bc] : cur0;
-      if (j + 1 < deg) issue_edge<G, S, AR>(cd, tp, cin, fb, f, e + 1, fs, any_decide, zl, eb[bn]);
+      const EdgeLoads<G, S, PACK> cur0 = eb[bc];
+      const EdgeLoads<G, S, PACK>& cur = TWO ? eb[bc] : cur0;
+      if (j + 1 < deg) issue_edge<G, S, AR, PACK>(cd, tp, cin, fb, f, e + 1, fs, any_decide, zl, eb[bn]);
       const int v = uni(cd.e_var[e]);
       const int eo = uni(cd.e_other[e]);
       const int h = uni(cd.e_label[e]);
@@ -534,14 +558,14 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
       double y64[P ? G::R : 1];
       if constexpr (P) {
 #pragma unroll
-        for (int r = 0; r < G::R; ++r) y64[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0 : 0.0) : gamma_inv_d(cur.x[r]);
+        for (int r = 0; r < G::R; ++r) y64[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0 : 0.0) : gamma_inv_d(cur.x(r));
         conv_prior_d<G>(y64, t);
 #pragma unroll
         for (int r = 0; r < G::R; ++r) st[j][r] = (float)y64[r];
       } else {
 #pragma unroll
         for (int r = 0; r < G::R; ++r)
-          st[j][r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
+          st[j][r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x(r));
         if constexpr (AR == kSymbolPrior) {
           conv_symbol_prior<G>(st[j], cur.pr, zl);
         } else if constexpr (AR == kProbPrior) {
@@ -553,7 +577,7 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
           if (any_decide && e < eo) {
             float xo[G::R];
 #pragma unroll
-            for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
+            for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o(r));
             int hd, fa, fo;
             const int ho = uni(cd.e_label[eo]);
             decide_pmf<G>(st[j], xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
@@ -571,7 +595,7 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
       if (AR != kProbPrior && any_decide && e < eo) {
         float xo[G::R];
 #pragma unroll
-        for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
+        for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o(r));
         int hd, fa, fo;
         const int ho = uni(cd.e_label[eo]);
         if constexpr (DM)
@@ -699,8 +723,8 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
     float st[G::R];
     if (j < deg) {
       const int e = e0 + j;
-      EdgeLoads<G, S> cur;
-      issue_edge<G, S, AR>(cd, tp, cin, fb, f, e, fs, any_decide, zl, cur);
+      EdgeLoads<G, S, true> cur;
+      issue_edge<G, S, AR, true>(cd, tp, cin, fb, f, e, fs, any_decide, zl, cur);
       const int v = uni(cd.e_var[e]);
       const int eo = uni(cd.e_other[e]);
       const int h = uni(cd.e_label[e]);
@@ -710,13 +734,13 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
       double y64[P ? G::R : 1];
       if constexpr (P) {
 #pragma unroll
-        for (int r = 0; r < G::R; ++r) y64[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0 : 0.0) : gamma_inv_d(cur.x[r]);
+        for (int r = 0; r < G::R; ++r) y64[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0 : 0.0) : gamma_inv_d(cur.x(r));
         conv_prior_d<G>(y64, t);
 #pragma unroll
         for (int r = 0; r < G::R; ++r) st[r] = (float)y64[r];
       } else {
 #pragma unroll
-        for (int r = 0; r < G::R; ++r) st[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x[r]);
+        for (int r = 0; r < G::R; ++r) st[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x(r));
         if constexpr (AR == kSymbolPrior) {
           conv_symbol_prior<G>(st, cur.pr, zl);
         } else if constexpr (AR == kProbPrior) {
@@ -726,7 +750,7 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
           if (any_decide && e < eo) {
             float xo[G::R];
 #pragma unroll
-            for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
+            for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o(r));
             int hd, fa, fo;
             const int ho = uni(cd.e_label[eo]);
             decide_pmf<G>(st, xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
@@ -744,7 +768,7 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
       if (AR != kProbPrior && any_decide && e < eo) {
         float xo[G::R];
 #pragma unroll
-        for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o[r]);
+        for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o(r));
         int hd, fa, fo;
         const int ho = uni(cd.e_label[eo]);
         decide<G>(st, xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
