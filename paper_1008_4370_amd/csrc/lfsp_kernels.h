@@ -910,11 +910,20 @@ __device__ __forceinline__ void syndrome_frames_body(const DevCode& cd, const ui
     for (int c = threadIdx.x; c < cd.M; c += blockDim.x) {
       const int e0 = cd.row_ptr[c], e1 = cd.row_ptr[c + 1];
       int s = 0, sf = 0;
-      for (int e = e0; e < e1; ++e) {
-        const uint32_t pk = cd.e_pack[e];
-        const int x = sh[pk & 0xFFFFFFu];
-        if (x) s ^= s_exp[s_log[pk >> 24] + s_log[x]];
-        sf ^= sw[e];
+      // the row's edges in groups of 8 whose loads are issued together (one
+      // memory latency per group, not one per edge); XOR sums in any order
+      for (int eb = e0; eb < e1; eb += 8) {
+        uint32_t pk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pk[u] = eb + u < e1 ? cd.e_pack[eb + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (eb + u < e1) {
+            const int x = sh[pk[u] & 0xFFFFFFu];
+            if (x) s ^= s_exp[s_log[pk[u] >> 24] + s_log[x]];
+            sf ^= sw[eb + u];
+          }
+        }
       }
       synd[(size_t)f * cd.M + c] = (uint8_t)s;
       if (fsynd) fsynd[(size_t)f * cd.M + c] = (uint8_t)sf;
