@@ -416,7 +416,7 @@ struct EdgeLoads<G, S, true> {
 };
 template <class G, typename S>
 struct EdgeLoads<G, S, false> {
-  float xf[G::R];
+  float xf[G::R];   // as above, converted to FP32 when loaded
   float of[G::R];
   float l[G::LOGQ];
   float pr[G::R];
@@ -529,14 +529,15 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
   Acc smag[G::R];
 #pragma unroll
   for (int r = 0; r < G::R; ++r) smag[r] = 0;
-  // edge j+1's loads are in flight while edge j is computed.  TWO: two load
-  // buffers indexed by the (unrolled, constant) parity of j, which saves the
-  // register copies of the one-buffer form (about 90 VALU moves per edge in
-  // the default arithmetic); used where the loop is unrolled whole and the
-  // kernel compiles without private-memory spills, the one-buffer form
-  // elsewhere.
-  // Packed loads where the edge loop unrolls whole (KMAX <= 8); with 16
-  // edges the one-buffer, converted form keeps the loop as it compiles best.
+  // Edge j+1's loads are in flight while edge j is computed.
+  // TWO: two load buffers indexed by the (unrolled, constant) parity of j;
+  // the one-buffer form copies the buffer being filled into the one being
+  // computed (cur0), about 90 VALU moves per edge in the default arithmetic.
+  // TWO is used where the loop unrolls whole and the kernel still compiles
+  // without private-memory spills.
+  // PACK: 16-bit messages stay packed until use where the loop unrolls whole
+  // (KMAX <= 8); with 16 edges the converted form compiles to less private
+  // memory.
   constexpr bool TWO = KMAX <= 8 && AR == kProbPrior && (G::LOGQ <= 6 || G::LOGR <= 3);
   constexpr bool PACK = KMAX <= 8;
   EdgeLoads<G, S, PACK> eb[TWO ? 2 : 1];
