@@ -11,8 +11,8 @@
 #include <type_traits>
 
 #include "ldpc_fd.h"
-#include "lfsp_kernels.h"
-#include "logsp_kernels.h"
+#include "frame_kernels.h"
+#include "launch.h"
 
 using namespace ldpcfd;
 
@@ -106,220 +106,44 @@ int32_t upload(ldpc_fd_code_s* c, const std::vector<T>& h, const T** out) {
   return LDPC_FD_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Kernel geometry selection.  Rows of weight <= 8 use 16 entries per lane
-// (L = Q/16 lanes per frame); heavier rows (<= 16) use 4 entries per lane so
-// that the per-check stash of k messages stays in registers.
-template <int LOGQ, int LOGR, int KMAX>
-struct Impl {
-  using G = Geo<LOGQ, LOGR>;
-  static constexpr int kWaves = 4;
-  static size_t lds() { return (size_t)kWaves * G::T * G::QP * sizeof(float); }
-  static unsigned blocks(long items) { return (unsigned)((items + kWaves - 1) / kWaves); }
-  static int frames_per_wave() { return G::T; }
-
-  static void var_plain(const DevCode& cd, int F, const float* llr, const float* c2v, float* v2c,
-                        uint8_t* hard, uint8_t* fsw, const uint32_t* active, int first, hipStream_t s) {
-    const long items = (long)((F + G::T - 1) / G::T) * cd.N;
-    if (items == 0) return;
-    hipLaunchKernelGGL(k_var_plain<G>, dim3(blocks(items)), dim3(64 * kWaves), lds(), s, cd, F, llr, c2v,
-                       v2c, hard, fsw, active, first);
-  }
-  static void check_plain(const DevCode& cd, int F, const float* v2c, float* c2v, const uint32_t* active,
-                          hipStream_t s) {
-    const long items = (long)((F + G::T - 1) / G::T) * cd.M;
-    if (items == 0) return;
-    hipLaunchKernelGGL((k_check_plain<G, KMAX>), dim3(blocks(items)), dim3(64 * kWaves), lds(), s, cd, F,
-                       v2c, c2v, active);
-  }
-  // Grid of the grid-stride fused pass: enough workgroups for the largest
-  // possible active list, capped, and a multiple of the XCD count.
-  static unsigned fused_blocks(const DevCode& cd, int Fmax, int cap) {
-    const long items = (long)((Fmax + G::T - 1) / G::T) * cd.M;
-    long b = std::min<long>(blocks(items), cap);
-    b = (b + kXcds - 1) / kXcds * kXcds;
-    return (unsigned)std::max<long>(b, kXcds);
-  }
-  // Edge-parallel pass (k_fused_split) over at most Fmax active frames: one
-  // workgroup of KMAX wavefronts per (frame group, check), grid-stride.
-  // ar: arithmetic form of the variable node (kFp32, kFp64, kSymbolPrior,
-  // kProbPrior).
-  template <typename S>
-  static void fused_split(const DevCode& cd, int Fmax, const float* prior, S* buf0, S* buf1, uint8_t* hard,
-                          uint8_t* fsw, const int* alist, const int* nact, const int* rnd, const int* maxit,
-                          int maxit_all, int ar, hipStream_t s) {
-    if (Fmax == 0) return;
-    const long items = (long)((Fmax + G::T - 1) / G::T) * cd.M;
-    const dim3 grid((unsigned)std::min<long>(items, 65536)), block(64 * KMAX);
-    const size_t lds_bytes = (size_t)2 * KMAX * G::T * G::QP * sizeof(float);
-    // built forms: FP64 variable node with FP32/FP16 storage, symbol priors
-    // with FP32 storage (the entry points reject the other combinations); the
-    // FP32 forms with every storage type
-    if constexpr (!std::is_same_v<S, bf16_t>) {
-      if (ar == kFp64) {
-        hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kFp64>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
-                           fsw, alist, nact, rnd, maxit, maxit_all);
-        return;
-      }
-    }
-    if (ar == kProbPrior) {
-      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kProbPrior>), grid, block, lds_bytes, s, cd, prior, buf0, buf1,
-                         hard, fsw, alist, nact, rnd, maxit, maxit_all);
-      return;
-    }
-    if constexpr (std::is_same_v<S, float>) {
-      if (ar == kSymbolPrior) {
-        hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kSymbolPrior>), grid, block, lds_bytes, s, cd, prior, buf0,
-                           buf1, hard, fsw, alist, nact, rnd, maxit, maxit_all);
-        return;
-      }
-    }
-      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, kFp32>), grid, block, lds_bytes, s, cd, prior, buf0, buf1, hard,
-                         fsw, alist, nact, rnd, maxit, maxit_all);
-  }
-  template <typename S>
-  static void fused(const DevCode& cd, int Fmax, const float* prior, S* buf0, S* buf1, uint8_t* hard, uint8_t* fsw,
-                    const int* alist, const int* nact, const int* rnd, const int* maxit, int maxit_all, int cap,
-                    int ar, bool mfma, hipStream_t s) {
-    if (Fmax == 0) return;
-    const dim3 grid(fused_blocks(cd, Fmax, cap)), block(64 * kWaves);
-    if constexpr (kMfmaDecision<G>) {
-      if (mfma && ar == kFp32) {
-        hipLaunchKernelGGL((k_fused<G, KMAX, S, kFp32, true>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
-                           alist, nact, rnd, maxit, maxit_all);
-        return;
-      }
-    }
-    if constexpr (!std::is_same_v<S, bf16_t>) {
-      if (ar == kFp64) {
-        hipLaunchKernelGGL((k_fused<G, KMAX, S, kFp64, false>), grid, block, lds(), s, cd, prior, buf0, buf1, hard,
-                           fsw, alist, nact, rnd, maxit, maxit_all);
-        return;
-      }
-    }
-    if (ar == kProbPrior) {
-      hipLaunchKernelGGL((k_fused<G, KMAX, S, kProbPrior, false>), grid, block, lds(), s, cd, prior, buf0, buf1,
-                         hard, fsw, alist, nact, rnd, maxit, maxit_all);
-      return;
-    }
-    if constexpr (std::is_same_v<S, float>) {
-      if (ar == kSymbolPrior) {
-        hipLaunchKernelGGL((k_fused<G, KMAX, S, kSymbolPrior, false>), grid, block, lds(), s, cd, prior, buf0, buf1,
-                           hard, fsw, alist, nact, rnd, maxit, maxit_all);
-        return;
-      }
-    }
-      hipLaunchKernelGGL((k_fused<G, KMAX, S, kFp32, false>), grid, block, lds(), s, cd, prior, buf0, buf1, hard, fsw,
-                         alist, nact, rnd, maxit, maxit_all);
-  }
-};
-
-// Kernel variant: rows of weight <= 8 have variants with 4, 8 or 16 entries
-// per lane (log2 R = 2, 3, 4; 16 entries only for q <= 128, where the kernel
-// keeps its stash in registers); rows of weight 9..16 use 4 or 8.
-template <int LOGQ, class Fn>
-bool dispatch_q(int kmax, int logr, Fn&& fn) {
-  if (kmax <= 8) {
-    if constexpr (LOGQ >= 4 && LOGQ <= 7) {
-      if (logr == 4) { fn(Impl<LOGQ, 4, 8>{}); return true; }
-    }
-    if constexpr (LOGQ >= 3) {
-      if (logr == 3) { fn(Impl<LOGQ, 3, 8>{}); return true; }
-    }
-    fn(Impl<LOGQ, 2, 8>{});
-    return true;
-  }
-  if (kmax <= 16) {
-    if constexpr (LOGQ >= 3) {
-      if (logr == 3) { fn(Impl<LOGQ, 3, 16>{}); return true; }
-    }
-    fn(Impl<LOGQ, 2, 16>{});
-    return true;
-  }
-  return false;
-}
-
-// Conventional log-domain SP kernels (LDPC_FD_MODE_LOGSP): one wavefront per
-// (frame, node), grid-stride over at most kLsBlocks workgroups.
-constexpr long kLsBlocks = 16384;
-
-template <int LOGQ>
-struct LogSp {
-  static unsigned grid(long items) { return (unsigned)std::max<long>(1, std::min(items, kLsBlocks)); }
-  // nf frames: alist[0..nf) (frames 0..nf-1 when alist is NULL)
-  static void check(const DevCode& cd, int nf, const int* alist, int kmax, const float* v2c, float* c2v,
-                    hipStream_t s) {
-    const long items = (long)nf * cd.M;
-    if (items == 0) return;
-    const size_t lds = (size_t)(3 * kmax + 1) * (1 << LOGQ) * sizeof(float);
-    hipLaunchKernelGGL(k_logsp_check<LOGQ>, dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, kmax, v2c, c2v);
-  }
-  static void var(const DevCode& cd, int jmax, int nf, const int* alist, const float* llr, const float* c2v,
-                  float* v2c, uint8_t* hard, uint8_t* fsw, int first, hipStream_t s) {
-    const long items = (long)nf * cd.N;
-    if (items == 0) return;
-    const size_t lds = (size_t)jmax * (1 << LOGQ) * sizeof(float);
-    hipLaunchKernelGGL(k_logsp_var<LOGQ>, dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, llr, c2v, v2c, hard,
-                       fsw, first);
-  }
-  // Log-Fourier (lin = false) or linear Fourier (lin = true) variable node for
-  // any column weight; same arguments as var
-  static void var_gen(const DevCode& cd, int jmax, int nf, const int* alist, const float* llr, const float* c2v,
-                      float* v2c, uint8_t* hard, uint8_t* fsw, int first, hipStream_t s, bool lin = false) {
-    const long items = (long)nf * cd.N;
-    if (items == 0) return;
-    const size_t lds = (size_t)jmax * (1 << LOGQ) * sizeof(float);
-    if (lin)
-      hipLaunchKernelGGL((k_var_gen<LOGQ, true>), dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, llr, c2v, v2c,
-                         hard, fsw, first);
-    else
-      hipLaunchKernelGGL((k_var_gen<LOGQ, false>), dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, llr, c2v,
-                         v2c, hard, fsw, first);
-  }
-  // linear Fourier SP check node (LDPC_FD_MODE_FSP)
-  static void fsp_check(const DevCode& cd, int nf, const int* alist, int kmax, const float* v2c, float* c2v,
-                        hipStream_t s) {
-    const long items = (long)nf * cd.M;
-    if (items == 0) return;
-    const size_t lds = (size_t)2 * kmax * (1 << LOGQ) * sizeof(float);
-    hipLaunchKernelGGL(k_fsp_check<LOGQ>, dim3(grid(items)), dim3(64), lds, s, cd, nf, alist, kmax, v2c, c2v);
-  }
-};
-
-template <class Fn>
-bool dispatch_logsp(int m, Fn&& fn) {
-  switch (m) {
-    case 2: fn(LogSp<2>{}); return true;
-    case 3: fn(LogSp<3>{}); return true;
-    case 4: fn(LogSp<4>{}); return true;
-    case 5: fn(LogSp<5>{}); return true;
-    case 6: fn(LogSp<6>{}); return true;
-    case 7: fn(LogSp<7>{}); return true;
-    case 8: fn(LogSp<8>{}); return true;
-    default: return false;
-  }
-}
-
-template <class Fn>
-bool dispatch(int m, int kmax, int logr, Fn&& fn) {
-  switch (m) {
-    case 2: return dispatch_q<2>(kmax, logr, fn);
-    case 3: return dispatch_q<3>(kmax, logr, fn);
-    case 4: return dispatch_q<4>(kmax, logr, fn);
-    case 5: return dispatch_q<5>(kmax, logr, fn);
-    case 6: return dispatch_q<6>(kmax, logr, fn);
-    case 7: return dispatch_q<7>(kmax, logr, fn);
-    case 8: return dispatch_q<8>(kmax, logr, fn);
-    default: return false;
-  }
-}
-
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Arithmetic form of the fused variable node for the PRECISE tuning value.
 int var_form(int precise) { return precise == 1 ? kFp64 : precise == 2 ? kProbPrior : kFp32; }
 
 size_t msg_bytes(int prec) { return prec == LDPC_FD_FP32 ? 4 : 2; }
+
+// Field-size dispatch of the templated kernels (defined per field size in
+// kernels_q.hip).
+bool run_fused(const ldpc_fd_code_s* c, int logr, const FusedArgs& a, hipStream_t s) {
+  return by_m(c->m, [&](auto M) { return fused_pass<decltype(M)::value>(c->kmax, logr, a, s); });
+}
+bool run_var_plain(const ldpc_fd_code_s* c, const PlainArgs& a, hipStream_t s) {
+  return by_m(c->m, [&](auto M) { return var_plain<decltype(M)::value>(c->kmax, c->logr, a, s); });
+}
+bool run_check_plain(const ldpc_fd_code_s* c, const PlainArgs& a, hipStream_t s) {
+  return by_m(c->m, [&](auto M) { return check_plain<decltype(M)::value>(c->kmax, c->logr, a, s); });
+}
+bool run_logsp_check(const ldpc_fd_code_s* c, const NodeArgs& a, hipStream_t s) {
+  return by_m(c->m, [&](auto M) { return logsp_check<decltype(M)::value>(a, s); });
+}
+bool run_logsp_var(const ldpc_fd_code_s* c, const NodeArgs& a, hipStream_t s) {
+  return by_m(c->m, [&](auto M) { return logsp_var<decltype(M)::value>(a, s); });
+}
+bool run_var_gen(const ldpc_fd_code_s* c, const NodeArgs& a, hipStream_t s) {
+  return by_m(c->m, [&](auto M) { return var_gen<decltype(M)::value>(a, s); });
+}
+bool run_fsp_check(const ldpc_fd_code_s* c, const NodeArgs& a, hipStream_t s) {
+  return by_m(c->m, [&](auto M) { return fsp_check<decltype(M)::value>(a, s); });
+}
+PlainArgs plain_args(const ldpc_fd_code_s* c, int F, const float* llr, const float* in, float* out, uint8_t* hard,
+                     uint8_t* fsw, const uint32_t* active, int first) {
+  return PlainArgs{c->dev, F, llr, in, out, hard, fsw, active, first};
+}
+NodeArgs node_args(const ldpc_fd_code_s* c, int nf, const int* alist, const float* llr, const float* in, float* out,
+                   uint8_t* hard, uint8_t* fsw, int first, bool lin = false) {
+  return NodeArgs{c->dev, nf, alist, c->kmax, c->jmax, llr, in, out, hard, fsw, first, lin};
+}
 
 // Workspace carving -------------------------------------------------------
 struct PlainWs {
@@ -660,22 +484,17 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     plain_layout(c, F, (char*)workspace, &w);
     hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, w.active, w.unsat, w.mism, (int*)nullptr,
                        (int*)nullptr, iters, status, (int*)nullptr, 0);
-    bool ok = dispatch_logsp(c->m, [&](auto impl) {
-      using I = decltype(impl);
-      timed(LDPC_FD_K_VAR, s, [&] { I::var(cd, c->jmax, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1, s); });
-    });
+    bool ok = true;
+    timed(LDPC_FD_K_VAR, s, [&] { ok = run_logsp_var(c, node_args(c, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1), s); });
     if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
     launch_quantise(c, F, w.v2c, 2, s);
     int nf = F;
     const int* list = nullptr;
     for (int ell = 1; ell <= max_iter; ++ell) {
-      dispatch_logsp(c->m, [&](auto impl) {
-        using I = decltype(impl);
-        timed(LDPC_FD_K_CHECK, s, [&] { I::check(cd, nf, list, c->kmax, w.v2c, w.c2v, s); });
-        launch_quantise(c, F, w.c2v, 2, s);
-        timed(LDPC_FD_K_VAR, s, [&] { I::var(cd, c->jmax, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0, s); });
-        launch_quantise(c, F, w.v2c, 2, s);
-      });
+      timed(LDPC_FD_K_CHECK, s, [&] { run_logsp_check(c, node_args(c, nf, list, nullptr, w.v2c, w.c2v, nullptr, nullptr, 0), s); });
+      launch_quantise(c, F, w.c2v, 2, s);
+      timed(LDPC_FD_K_VAR, s, [&] { run_logsp_var(c, node_args(c, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0), s); });
+      launch_quantise(c, F, w.v2c, 2, s);
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
       hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,
@@ -700,31 +519,19 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     plain_layout(c, F, (char*)workspace, &w);
     hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, w.active, w.unsat, w.mism, (int*)nullptr,
                        (int*)nullptr, iters, status, (int*)nullptr, 0);
-    bool ok = dispatch_logsp(c->m, [&](auto impl) {
-      using I = decltype(impl);
-      timed(LDPC_FD_K_VAR, s, [&] { I::var_gen(cd, c->jmax, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1, s, lin); });
-    });
+    bool ok = true;
+    timed(LDPC_FD_K_VAR, s, [&] { ok = run_var_gen(c, node_args(c, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1, lin), s); });
     if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
     launch_quantise(c, F, w.v2c, qk, s);
     int nf = F;
     const int* list = nullptr;
     for (int ell = 1; ell <= max_iter; ++ell) {
-      if (lin) {
-        dispatch_logsp(c->m, [&](auto impl) {
-          using I = decltype(impl);
-          timed(LDPC_FD_K_CHECK, s, [&] { I::fsp_check(cd, nf, list, c->kmax, w.v2c, w.c2v, s); });
-        });
-      } else {
-        dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
-          using I = decltype(impl);
-          timed(LDPC_FD_K_CHECK, s, [&] { I::check_plain(cd, F, w.v2c, w.c2v, w.active, s); });
-        });
-      }
+      if (lin)
+        timed(LDPC_FD_K_CHECK, s, [&] { run_fsp_check(c, node_args(c, nf, list, nullptr, w.v2c, w.c2v, nullptr, nullptr, 0), s); });
+      else
+        timed(LDPC_FD_K_CHECK, s, [&] { run_check_plain(c, plain_args(c, F, nullptr, w.v2c, w.c2v, nullptr, nullptr, w.active, 0), s); });
       launch_quantise(c, F, w.c2v, qk, s);
-      dispatch_logsp(c->m, [&](auto impl) {
-        using I = decltype(impl);
-        timed(LDPC_FD_K_VAR, s, [&] { I::var_gen(cd, c->jmax, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0, s, lin); });
-      });
+      timed(LDPC_FD_K_VAR, s, [&] { run_var_gen(c, node_args(c, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0, lin), s); });
       launch_quantise(c, F, w.v2c, qk, s);
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
@@ -744,20 +551,15 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     plain_layout(c, F, (char*)workspace, &w);
     hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, w.active, w.unsat, w.mism, (int*)nullptr,
                        (int*)nullptr, iters, status, (int*)nullptr, 0);
-    bool ok = dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
-      using I = decltype(impl);
-      timed(LDPC_FD_K_VAR, s, [&] { I::var_plain(cd, F, llr, nullptr, w.v2c, hard, w.fsw, w.active, 1, s); });
-    });
+    bool ok = true;
+    timed(LDPC_FD_K_VAR, s, [&] { ok = run_var_plain(c, plain_args(c, F, llr, nullptr, w.v2c, hard, w.fsw, w.active, 1), s); });
     launch_quantise(c, F, w.v2c, 0, s);
     if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
     for (int ell = 1; ell <= max_iter; ++ell) {
-      dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
-        using I = decltype(impl);
-        timed(LDPC_FD_K_CHECK, s, [&] { I::check_plain(cd, F, w.v2c, w.c2v, w.active, s); });
-        launch_quantise(c, F, w.c2v, 0, s);
-        timed(LDPC_FD_K_VAR, s, [&] { I::var_plain(cd, F, llr, w.c2v, w.v2c, hard, w.fsw, w.active, 0, s); });
-        launch_quantise(c, F, w.v2c, 0, s);
-      });
+      timed(LDPC_FD_K_CHECK, s, [&] { run_check_plain(c, plain_args(c, F, nullptr, w.v2c, w.c2v, nullptr, nullptr, w.active, 0), s); });
+      launch_quantise(c, F, w.c2v, 0, s);
+      timed(LDPC_FD_K_VAR, s, [&] { run_var_plain(c, plain_args(c, F, llr, w.c2v, w.v2c, hard, w.fsw, w.active, 0), s); });
+      launch_quantise(c, F, w.v2c, 0, s);
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
       hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,
@@ -787,24 +589,10 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   auto enqueue_round = [&](hipStream_t st, hipEvent_t e0, hipEvent_t e1, int lr, bool tail) {
     bool ok = true;
     if (e0) (void)hipEventRecord(e0, st);
-    ok = dispatch(c->m, c->kmax, lr, [&](auto impl) {
-      using I = decltype(impl);
-      auto run = [&](auto* b0, auto* b1) {
-        using S = std::remove_pointer_t<decltype(b0)>;
-        if (tail && c->split)
-          I::template fused_split<S>(cd, std::min(F, std::max(c->tail_frames, 1)), tp, b0, b1, hard, w.fsw,
-                                     w.alist, w.nact, w.rnd, nullptr, max_iter, ar, st);
-        else
-          I::template fused<S>(cd, F, tp, b0, b1, hard, w.fsw, w.alist, w.nact, w.rnd, nullptr, max_iter,
-                               c->blocks, ar, c->mfma, st);
-      };
-      if (prec == LDPC_FD_FP32)
-        run((float*)w.buf[0], (float*)w.buf[1]);
-      else if (prec == LDPC_FD_FP16)
-        run((_Float16*)w.buf[0], (_Float16*)w.buf[1]);
-      else
-        run((bf16_t*)w.buf[0], (bf16_t*)w.buf[1]);
-    });
+    const bool split = tail && c->split;
+    const FusedArgs fa{cd, split ? std::min(F, std::max(c->tail_frames, 1)) : F, tp, w.buf[0], w.buf[1], hard,
+                       w.fsw, w.alist, w.nact, w.rnd, nullptr, max_iter, c->blocks, ar, c->mfma != 0, prec, split};
+    ok = run_fused(c, lr, fa, st);
     if (e1) (void)hipEventRecord(e1, st);
     launch_syndrome_retire(c, F, hard, w.fsw, synd, w.unsat, w.mism, w.alist, w.nact, w.rnd, max_iter, nullptr, w.tmp,
                            iters, status, nullptr, nullptr, tail ? std::max(c->tail_frames, 1) : 0, st);
@@ -956,61 +744,55 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, active, unsat, mism, alist, nact, (int32_t*)nullptr,
                      (uint32_t*)nullptr, rnd, c2v_in ? 1 : 0);
   launch_prior(c, F, llr, prior, s);
-  bool ok = mode == LDPC_FD_MODE_LOGSP ? dispatch_logsp(c->m, [&](auto impl) {
-    using I = decltype(impl);
-    I::var(cd, c->jmax, F, nullptr, llr, c2v_in, v2c_out, hard, fsw, c2v_in ? 0 : 1, s);
+  bool ok = true;
+  const int first = c2v_in ? 0 : 1;
+  if (mode == LDPC_FD_MODE_LOGSP) {
+    ok = run_logsp_var(c, node_args(c, F, nullptr, llr, c2v_in, v2c_out, hard, fsw, first), s);
     launch_quantise(c, F, v2c_out, 2, s);
     if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
-    I::check(cd, F, nullptr, c->kmax, v2c_out, c2v_out, s);
+    ok = ok && run_logsp_check(c, node_args(c, F, nullptr, nullptr, v2c_out, c2v_out, nullptr, nullptr, 0), s);
     launch_quantise(c, F, c2v_out, 2, s);
-  }) : dispatch(c->m, c->kmax, c->logr, [&](auto impl) {
-    using I = decltype(impl);
-    if (mode == LDPC_FD_MODE_FSP || (mode == LDPC_FD_MODE_PLAIN && !c->regular)) {
-      const bool lin = mode == LDPC_FD_MODE_FSP;
-      dispatch_logsp(c->m, [&](auto gen) {
-        using GI = decltype(gen);
-        GI::var_gen(cd, c->jmax, F, nullptr, llr, c2v_in, v2c_out, hard, fsw, c2v_in ? 0 : 1, s, lin);
-        launch_quantise(c, F, v2c_out, lin ? 1 : 0, s);
-        if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
-        if (lin)
-          GI::fsp_check(cd, F, nullptr, c->kmax, v2c_out, c2v_out, s);
-        else
-          I::check_plain(cd, F, v2c_out, c2v_out, nullptr, s);
-        launch_quantise(c, F, c2v_out, lin ? 1 : 0, s);
-      });
-    } else if (mode == LDPC_FD_MODE_PLAIN) {
-      I::var_plain(cd, F, llr, c2v_in, v2c_out, hard, fsw, nullptr, c2v_in ? 0 : 1, s);
-      launch_quantise(c, F, v2c_out, 0, s);
-      if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
-      I::check_plain(cd, F, v2c_out, c2v_out, nullptr, s);
-      launch_quantise(c, F, c2v_out, 0, s);
-    } else {
-      // Frames at round 1 read buffer 1 and write buffer 0; frames at round 0
-      // (no imported state) write buffer 1.  16-bit storage: the imported state
-      // is rounded to the storage type first and the result widened back.
-      auto run = [&](auto tag) {
-        using S = decltype(tag);
-        S* in = (S*)c2v_in;
-        S* out = (S*)c2v_out;
-        const unsigned g = (unsigned)std::min<size_t>((n_msg / 4 + 255) / 256, 65536);
-        if (prec != LDPC_FD_FP32) {
-          in = (S*)st_in;
-          out = (S*)st_out;
-          if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, in, n_msg / 4);
-        }
-        if (c2v_in)
-          I::template fused<S>(cd, F, prior, out, in, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, var_form(c->precise), c->mfma, s);
-        else
-          I::template fused<S>(cd, F, prior, nullptr, out, hard, fsw, alist, nact, rnd, nullptr, 1 << 30, c->blocks, var_form(c->precise), c->mfma, s);
-        if (prec != LDPC_FD_FP32)
-          hipLaunchKernelGGL((k_convert<S, float>), dim3(g), dim3(256), 0, s, (const S*)out, c2v_out, n_msg / 4);
-      };
-      if (prec == LDPC_FD_FP32) run(float{});
-      else if (prec == LDPC_FD_FP16) run(_Float16{});
-      else run(bf16_t{});
-      if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, alist, nact, nullptr, s, rnd);
-    }
-  });
+  } else if (mode == LDPC_FD_MODE_FSP || (mode == LDPC_FD_MODE_PLAIN && !c->regular)) {
+    const bool lin = mode == LDPC_FD_MODE_FSP;
+    ok = run_var_gen(c, node_args(c, F, nullptr, llr, c2v_in, v2c_out, hard, fsw, first, lin), s);
+    launch_quantise(c, F, v2c_out, lin ? 1 : 0, s);
+    if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
+    if (lin)
+      ok = ok && run_fsp_check(c, node_args(c, F, nullptr, nullptr, v2c_out, c2v_out, nullptr, nullptr, 0), s);
+    else
+      ok = ok && run_check_plain(c, plain_args(c, F, nullptr, v2c_out, c2v_out, nullptr, nullptr, nullptr, 0), s);
+    launch_quantise(c, F, c2v_out, lin ? 1 : 0, s);
+  } else if (mode == LDPC_FD_MODE_PLAIN) {
+    ok = run_var_plain(c, plain_args(c, F, llr, c2v_in, v2c_out, hard, fsw, nullptr, first), s);
+    launch_quantise(c, F, v2c_out, 0, s);
+    if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, nullptr, nullptr, nullptr, s);
+    ok = ok && run_check_plain(c, plain_args(c, F, nullptr, v2c_out, c2v_out, nullptr, nullptr, nullptr, 0), s);
+    launch_quantise(c, F, c2v_out, 0, s);
+  } else {
+    // Frames at round 1 read buffer 1 and write buffer 0; frames at round 0
+    // (no imported state) write buffer 1.  16-bit storage: the imported state
+    // is rounded to the storage type first and the result widened back.
+    auto run = [&](auto tag) {
+      using S = decltype(tag);
+      S* in = (S*)c2v_in;
+      S* out = (S*)c2v_out;
+      const unsigned g = (unsigned)std::min<size_t>((n_msg / 4 + 255) / 256, 65536);
+      if (prec != LDPC_FD_FP32) {
+        in = (S*)st_in;
+        out = (S*)st_out;
+        if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, in, n_msg / 4);
+      }
+      const FusedArgs fa{cd, F, prior, c2v_in ? (void*)out : nullptr, c2v_in ? (void*)in : (void*)out, hard, fsw,
+                         alist, nact, rnd, nullptr, 1 << 30, c->blocks, var_form(c->precise), c->mfma != 0, prec, false};
+      ok = run_fused(c, c->logr, fa, s);
+      if (prec != LDPC_FD_FP32)
+        hipLaunchKernelGGL((k_convert<S, float>), dim3(g), dim3(256), 0, s, (const S*)out, c2v_out, n_msg / 4);
+    };
+    if (prec == LDPC_FD_FP32) run(float{});
+    else if (prec == LDPC_FD_FP16) run(_Float16{});
+    else run(bf16_t{});
+    if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, alist, nact, nullptr, s, rnd);
+  }
   hipError_t e1 = hipStreamSynchronize(s);
   hipError_t e2 = hipFree(tmp);
   if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");

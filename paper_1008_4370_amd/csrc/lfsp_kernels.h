@@ -824,290 +824,4 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
   }
 }
 
-// Syndromes of the tentative decision, for codes whose rows do not fit in LDS
-// (one thread per (active frame, check)): direct s_c = sum_{v in V_c} h_cv x^_v
-// and Fourier word = XOR of per-edge sign words.  Flags the frame when either
-// is nonzero or they differ (unsat / mism must be zero on entry).
-__global__ void k_syndrome(DevCode cd, const uint8_t* __restrict__ hard, const uint8_t* __restrict__ fsw,
-                           uint8_t* __restrict__ synd, uint8_t* __restrict__ fsynd,
-                           uint32_t* __restrict__ unsat, uint32_t* __restrict__ mism,
-                           const int* __restrict__ alist, const int* __restrict__ nact_p, int F_all,
-                           const uint32_t* __restrict__ active, const int* __restrict__ rnd) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int nact = nact_p ? *nact_p : F_all;
-  if (i >= (long)nact * cd.M) return;
-  const int slot = (int)(i / cd.M), c = (int)(i % cd.M);
-  const int f = alist ? alist[slot] : slot;
-  if (active && !active[f]) return;
-  if (rnd && rnd[f] == 0) return;
-  const int e0 = cd.row_ptr[c], e1 = cd.row_ptr[c + 1];
-  int s = 0, sf = 0;
-  for (int e = e0; e < e1; ++e) {
-    const int x = hard[(size_t)f * cd.N + cd.e_var[e]];
-    if (x) s ^= cd.gexp[cd.glog[cd.e_label[e]] + cd.glog[x]];
-    sf ^= fsw[(size_t)f * cd.E + e];
-  }
-  synd[(size_t)f * cd.M + c] = (uint8_t)s;
-  if (fsynd) fsynd[(size_t)f * cd.M + c] = (uint8_t)sf;
-  if (s | sf) atomicOr(&unsat[f], 1u);
-  if (s != sf) atomicOr(&mism[f], 1u);
-}
-
-// INITIALIZATION (Sec. 3.2): the initial message Lambda_v^(0) is Gamma of the
-// Fourier transform of the channel pmf, which for BPSK factors over the bits:
-// P_v^(0)(z) = prod_{i in z} tanh(L_{v,i}/2).  The passes keep only these m
-// factors per symbol (the same 4 N m bytes as the LLRs) and apply them as the
-// prior convolution; this kernel forms them once per decode.
-// comp != 0: the signed complement sign(L) (1 - |tanh(L/2)|) = sign(L) 2 e / (1 + e)
-// instead (precise variable node), exact in FP32 relative precision for reliable bits.
-__device__ __forceinline__ float prior_factor(float x, int comp) {
-  const float e = __builtin_amdgcn_exp2f(-1.4426950408889634f * __builtin_fabsf(x));  // e^-|L|
-  return __builtin_copysignf((comp ? 2.0f * e : 1.0f - e) / (1.0f + e), x);
-}
-
-__global__ void k_prior_factors(const float* __restrict__ llr, float* __restrict__ t, size_t n, int comp) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    t[i] = prior_factor(llr[i], comp);
-}
-
-// Syndromes of the tentative decision, one workgroup per active frame: the
-// frame's hard decisions and per-edge Fourier sign words are staged in LDS
-// (word loads when the rows are word aligned), the field tables once per
-// workgroup; each thread then forms checks c = tid, tid + 256, ...: direct
-// s_c = sum_{v in V_c} h_cv x^_v and the Fourier word = XOR of the check's
-// edge words (edges of a check are contiguous).  unsat[f] / mism[f] are set to
-// whether any check is nonzero / any pair differs.
-__device__ __forceinline__ void syndrome_frames_body(const DevCode& cd, const uint8_t* __restrict__ hard,
-                                                     const uint8_t* __restrict__ fsw, uint8_t* __restrict__ synd,
-                                                     uint8_t* __restrict__ fsynd, uint32_t* __restrict__ unsat,
-                                                     uint32_t* __restrict__ mism, const int* __restrict__ alist,
-                                                     int nact, const uint32_t* __restrict__ active,
-                                                     const int* __restrict__ rnd, uint32_t* smw, uint8_t* s_exp,
-                                                     uint16_t* s_log) {
-  uint8_t* sh = reinterpret_cast<uint8_t*>(smw);   // [N] (rounded up to words)
-  const int nw = (cd.N + 3) >> 2, ew = (cd.E + 3) >> 2;
-  uint8_t* sw = reinterpret_cast<uint8_t*>(smw + nw);  // [E]
-  for (int i = threadIdx.x; i < 512; i += blockDim.x) s_exp[i] = cd.gexp[i];
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) s_log[i] = cd.glog[i];
-  const bool wN = (cd.N & 3) == 0, wE = (cd.E & 3) == 0;
-  for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
-    const int f = alist ? alist[slot] : slot;
-    if (active && !active[f]) continue;  // uniform over the block
-    if (rnd && rnd[f] == 0) continue;     // fresh frame: no decision this pass
-    if (wN) {
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(hard + (size_t)f * cd.N);
-      for (int i = threadIdx.x; i < nw; i += blockDim.x) smw[i] = src[i];
-    } else {
-      for (int i = threadIdx.x; i < cd.N; i += blockDim.x) sh[i] = hard[(size_t)f * cd.N + i];
-    }
-    if (wE) {
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(fsw + (size_t)f * cd.E);
-      for (int i = threadIdx.x; i < ew; i += blockDim.x) smw[nw + i] = src[i];
-    } else {
-      for (int i = threadIdx.x; i < cd.E; i += blockDim.x) sw[i] = fsw[(size_t)f * cd.E + i];
-    }
-    __syncthreads();
-    int bad = 0, mm = 0;
-    for (int c = threadIdx.x; c < cd.M; c += blockDim.x) {
-      const int e0 = cd.row_ptr[c], e1 = cd.row_ptr[c + 1];
-      int s = 0, sf = 0;
-      // the row's edges in groups of 8 whose loads are issued together (one
-      // memory latency per group, not one per edge); XOR sums in any order
-      for (int eb = e0; eb < e1; eb += 8) {
-        uint32_t pk[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) pk[u] = eb + u < e1 ? cd.e_pack[eb + u] : 0u;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (eb + u < e1) {
-            const int x = sh[pk[u] & 0xFFFFFFu];
-            if (x) s ^= s_exp[s_log[pk[u] >> 24] + s_log[x]];
-            sf ^= sw[eb + u];
-          }
-        }
-      }
-      synd[(size_t)f * cd.M + c] = (uint8_t)s;
-      if (fsynd) fsynd[(size_t)f * cd.M + c] = (uint8_t)sf;
-      bad |= s | sf;
-      mm |= s != sf;
-    }
-    bad = __syncthreads_or(bad);
-    mm = __syncthreads_or(mm);
-    if (threadIdx.x == 0) {
-      unsat[f] = bad ? 1u : 0u;
-      mism[f] = mm ? 1u : 0u;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_syndrome_frames(DevCode cd, const uint8_t* __restrict__ hard,
-                                                         const uint8_t* __restrict__ fsw,
-                                                         uint8_t* __restrict__ synd, uint8_t* __restrict__ fsynd,
-                                                         uint32_t* __restrict__ unsat, uint32_t* __restrict__ mism,
-                                                         const int* __restrict__ alist,
-                                                         const int* __restrict__ nact_p, int F_all,
-                                                         const uint32_t* __restrict__ active,
-                                                         const int* __restrict__ rnd) {
-  extern __shared__ uint32_t smw[];
-  __shared__ uint8_t s_exp[512];
-  __shared__ uint16_t s_log[256];
-  syndrome_frames_body(cd, hard, fsw, synd, fsynd, unsat, mism, alist, nact_p ? *nact_p : F_all, active, rnd, smw,
-                       s_exp, s_log);
-}
-
-// Elementwise conversion between message storage types (n4 groups of 4).
-template <typename Sin, typename Sout>
-__global__ void k_convert(const Sin* __restrict__ in, Sout* __restrict__ out, size_t n4) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
-    float v[4];
-    IO<Sin>::load4(in + 4 * i, v);
-    IO<Sout>::store4(out + 4 * i, v);
-  }
-}
-
-// Initial per-frame state; nact[2] (the syndrome/retire ticket of the fused
-// decoder's workspace) is cleared with the active count.
-__global__ void k_init_frames(int F, uint32_t* active, uint32_t* unsat, uint32_t* mism, int* alist,
-                              int* nact, int32_t* iters, uint32_t* status, int* rnd, int rnd0) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f == 0 && nact) {
-    nact[0] = F;
-    nact[2] = 0;
-  }
-  if (f >= F) return;
-  if (rnd) rnd[f] = rnd0;
-  if (active) active[f] = 1u;
-  unsat[f] = 0u;
-  mism[f] = 0u;
-  if (alist) alist[f] = f;
-  if (iters) iters[f] = 0;
-  if (status) status[f] = 0u;
-}
-
-// PLAIN and LOGSP decoders: stopping rule for round ell over all frames; with
-// alist, the frames that continue are appended to it (in counter order).
-__global__ void k_retire_plain(int F, int ell, int max_iter, uint32_t* active, uint32_t* unsat,
-                               uint32_t* mism, int32_t* iters, uint32_t* status, uint32_t* count, int* alist) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= F || !active[f]) return;
-  iters[f] = ell;
-  uint32_t st = status[f] | (mism[f] ? 2u : 0u);
-  if (!unsat[f]) {
-    st |= 1u;
-    active[f] = 0u;
-  } else if (ell >= max_iter) {
-    active[f] = 0u;
-  } else {
-    const uint32_t slot = atomicAdd(count, 1u);
-    if (alist) alist[slot] = f;
-  }
-  status[f] = st;
-  unsat[f] = 0u;
-  mism[f] = 0u;
-}
-
-// FUSED decoder: stopping rule and stable compaction of the active list by one
-// workgroup of NT threads.  For each active frame with l = rnd[f] >= 1 the
-// decision of round l was formed in the pass: iters = l; the frame stops when
-// both syndromes were zero, or fails at l = max_iter.  Continuing frames
-// advance rnd.  Stopped frames are appended to `done` (when given) for
-// harvesting.
-template <int NT>
-__device__ __forceinline__ void retire_compact_body(int maxit_all, const int* __restrict__ maxit, int* alist,
-                                                    int* tmp, int* nact_p, uint32_t* unsat, uint32_t* mism,
-                                                    int32_t* iters, uint32_t* status, int* rnd, int* done,
-                                                    int* ndone, int* wsum, int* base_s) {
-  constexpr int NW = NT / 64;
-  const int nact = *nact_p;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid == 0) *base_s = 0;
-  __syncthreads();
-  for (int start = 0; start < nact; start += NT) {
-    const int i = start + tid;
-    int keep = 0, f = -1, stop = 0;
-    if (i < nact) {
-      f = alist[i];
-      const int ell = rnd[f];
-      if (ell >= 1) {
-        iters[f] = ell;
-        uint32_t st = status[f] | (mism[f] ? 2u : 0u);
-        const bool conv = !unsat[f];
-        if (conv) st |= 1u;
-        status[f] = st;
-        unsat[f] = 0u;
-        mism[f] = 0u;
-        keep = !conv && ell < (maxit ? maxit[f] : maxit_all);
-      } else {
-        keep = 1;
-      }
-      if (keep) rnd[f] = ell + 1;
-      stop = !keep;
-    }
-    if (done && stop) done[atomicAdd(ndone, 1)] = f;
-    const uint64_t b = __builtin_amdgcn_ballot_w64(keep);
-    const int pre = __builtin_popcountll(b & ((1ull << lane) - 1ull));
-    if (lane == 0) wsum[w] = __builtin_popcountll(b);
-    __syncthreads();
-    int off = *base_s;
-    for (int k = 0; k < w; ++k) off += wsum[k];
-    if (keep) tmp[off + pre] = f;
-    __syncthreads();
-    if (tid == 0) {
-      int s2 = 0;
-      for (int k = 0; k < NW; ++k) s2 += wsum[k];
-      *base_s += s2;
-    }
-    __syncthreads();
-  }
-  const int total = *base_s;
-  for (int i = tid; i < total; i += NT) alist[i] = tmp[i];
-  __syncthreads();
-  if (tid == 0) *nact_p = total;
-}
-
-// The same as a kernel of one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_retire_compact(int maxit_all, const int* __restrict__ maxit, int* alist,
-                                                         int* tmp, int* nact_p, uint32_t* unsat, uint32_t* mism,
-                                                         int32_t* iters, uint32_t* status, int* rnd, int* done,
-                                                         int* ndone) {
-  __shared__ int wsum[16];
-  __shared__ int base_s;
-  retire_compact_body<1024>(maxit_all, maxit, alist, tmp, nact_p, unsat, mism, iters, status, rnd, done, ndone,
-                            wsum, &base_s);
-}
-
-// Syndromes of the active frames and, in the workgroup that finishes last, the
-// stopping rule and compaction (k_retire_compact's work), in one launch: every
-// workgroup that checked a frame publishes its flags (device-scope release),
-// every workgroup takes a ticket, and the holder of the last ticket acquires
-// the flags and retires.  No workgroup waits for another.  A release writes
-// back the XCD's L2, so this form is for passes with few active frames (a few
-// releases); *ticket is zero on entry and reset by the last workgroup.
-__global__ __launch_bounds__(256) void k_syndrome_retire(DevCode cd, const uint8_t* __restrict__ hard,
-                                                         const uint8_t* __restrict__ fsw, uint8_t* __restrict__ synd,
-                                                         uint32_t* unsat, uint32_t* mism, int* alist, int* nact_p,
-                                                         int* rnd, int maxit_all, const int* __restrict__ maxit,
-                                                         int* tmp, int32_t* iters, uint32_t* status, int* done,
-                                                         int* ndone, unsigned* ticket) {
-  extern __shared__ uint32_t smw[];
-  __shared__ uint8_t s_exp[512];
-  __shared__ uint16_t s_log[256];
-  __shared__ int wsum[4];
-  __shared__ int base_s;
-  __shared__ int last;
-  const int nact = *nact_p;
-  syndrome_frames_body(cd, hard, fsw, synd, nullptr, unsat, mism, alist, nact, nullptr, rnd, smw, s_exp, s_log);
-  // thread 0 wrote this workgroup's flags (after the body's last barrier)
-  if (threadIdx.x == 0) {
-    if ((int)blockIdx.x < nact) __threadfence();
-    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  retire_compact_body<256>(maxit_all, maxit, alist, tmp, nact_p, unsat, mism, iters, status, rnd, done, ndone, wsum,
-                           &base_s);
-  if (threadIdx.x == 0) *ticket = 0u;
-}
-
 }  // namespace ldpcfd

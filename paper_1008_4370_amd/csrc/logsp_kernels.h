@@ -615,32 +615,4 @@ __global__ __launch_bounds__(64) void k_fsp_check(DevCode cd, int nf, const int*
   }
 }
 
-// Low-bit message storage, emulated in place on FP32 message arrays: every
-// stored word is replaced by the nearest word of a b-bit format.
-//   kind 0 (Log-Fourier words, sign | -log2|P|): the sign and a (b-1)-bit
-//     unsigned magnitude on the grid {0, step, ..., (2^(b-1) - 1) step}
-//     (round to nearest, saturating);
-//   kind 1 (linear Fourier values P in [-1, 1]): b-bit two's complement
-//     fixed point with step 2^-(b-1) (round to nearest, saturating at
-//     +-(1 - 2^-(b-1)) and -1);
-//   kind 2 (Log-SP log2 pmfs, <= 0): b-bit unsigned -k * step, k = 0 ..
-//     2^b - 1 (round to nearest, saturating).
-__global__ void k_quantise(float* __restrict__ w, size_t n, int kind, int bits, float step) {
-  const float top = (float)((1 << (bits - 1)) - 1);
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const float x = w[i];
-    if (kind == 0) {
-      const float k = __builtin_fminf(__builtin_rintf(__builtin_fabsf(x) / step), top);
-      w[i] = __builtin_copysignf(k * step, x);
-    } else if (kind == 2) {
-      const float k = __builtin_fminf(__builtin_rintf(-x / step), (float)((1 << bits) - 1));
-      w[i] = -k * step;
-    } else {
-      const float sc = (float)(1 << (bits - 1));
-      const float k = __builtin_fminf(__builtin_fmaxf(__builtin_rintf(x * sc), -sc), top);
-      w[i] = k / sc;
-    }
-  }
-}
-
 }  // namespace ldpcfd
