@@ -291,9 +291,28 @@ class Pool:
         return n.value
 
     def submit(self, k: int, llr, tags, max_iter: int) -> int:
-        """Admit frames llr [n, N, m] (device float32) of code k; returns the number taken."""
+        """Admit frames llr [n, N, m] (device float32, contiguous) of code k;
+        returns the number taken.  The library reads n * N * m floats from
+        llr's pointer, so the shape, type, device and layout are checked here
+        (ValueError) before the call."""
+        import torch
+        if not 0 <= k < len(self.codes):
+            raise ValueError(f"code index {k} outside 0..{len(self.codes) - 1}")
+        code = self.codes[k]
+        if not isinstance(llr, torch.Tensor):
+            raise ValueError("llr must be a torch tensor")
+        if llr.dtype != torch.float32:
+            raise ValueError(f"llr must be float32, not {llr.dtype}")
+        if llr.dim() != 3 or tuple(llr.shape[1:]) != (code.N, code.m):
+            raise ValueError(f"llr must have shape [n, {code.N}, {code.m}], not {tuple(llr.shape)}")
+        if not llr.is_contiguous():
+            raise ValueError("llr must be contiguous")
+        if not llr.is_cuda:
+            raise ValueError("llr must be in device memory")
         n = int(llr.shape[0])
         t = np.ascontiguousarray(np.asarray(tags, dtype=np.uint64)) if tags is not None else None
+        if t is not None and (t.ndim != 1 or t.shape[0] < n):
+            raise ValueError(f"tags must hold at least {n} entries")
         got = _i32()
         _check(lib().ldpc_fd_pool_submit(self.handle, k, _ptr(llr), n,
                                          None if t is None else t.ctypes.data, int(max_iter), ctypes.byref(got)))

@@ -65,3 +65,29 @@ def test_column_weight_limit():
     col = [x for r in range(17) for x in (0, r + 1)]
     got, err = _create(17, 18, 3, rp, col, [1] * 34)
     assert got == d.E_UNSUPPORTED and "column weight" in err
+
+
+def test_pool_submit_rejects_bad_llr_before_the_library_call():
+    """Pool.submit checks type, shape, layout, device and tags before handing the
+    pointer to ldpc_fd_pool_submit (which reads n * N * m floats from it)."""
+    import types
+
+    torch = pytest.importorskip("torch")
+    pool = d.Pool.__new__(d.Pool)
+    pool.codes = [types.SimpleNamespace(N=12, m=3)]
+    pool.handle = None
+    good = torch.zeros((4, 12, 3), dtype=torch.float32)
+    bad = [
+        (np.zeros((4, 12, 3), np.float32), "torch tensor"),
+        (good.to(torch.float16), "float32"),
+        (torch.zeros((4, 11, 3), dtype=torch.float32), "shape"),
+        (torch.zeros((4, 12), dtype=torch.float32), "shape"),
+        (torch.zeros((4, 3, 12), dtype=torch.float32).transpose(1, 2), "contiguous"),
+        (good, "device memory"),   # a host tensor (this container has no GPU)
+    ]
+    for llr, msg in bad:
+        with pytest.raises(ValueError, match=msg):
+            pool.submit(0, llr, None, 10)
+    with pytest.raises(ValueError, match="code index"):
+        pool.submit(1, good, None, 10)
+    pool.handle = None
