@@ -188,6 +188,26 @@ int32_t ldpc_fd_round(ldpc_fd_code code, int32_t frames, const float *llr, const
                       float *v2c_out, float *c2v_out, uint8_t *hard, uint8_t *fsynd,
                       uint8_t *synd, int32_t mode, int32_t prec, void *stream);
 
+/* ldpc_fd_round for callers that cannot allocate device memory: code recorded
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results as ldpc_fd_round; the
+ * temporaries come from a static device array of LDPC_FD_ROUND_SCRATCH_BYTES
+ * (64 MiB) that the library holds on every GPU it runs on until the process
+ * ends, so the call allocates and frees nothing and does not synchronise: the
+ * work is enqueued on `stream` and the outputs are valid once the stream has
+ * passed it.  Every call on one GPU uses that GPU's same array (the library
+ * re-initialises whatever must start at zero on every call), so calls that
+ * overlap on one GPU, on different streams or threads, race and must be
+ * ordered by the caller.  The scratch need grows with frames, E, 2^m and, for
+ * 16-bit storage, with the staging of the state (GF(64) N=1000: ~26 KB per
+ * frame with FP32 storage, ~540 KB with FP16/BF16).
+ * Errors: as ldpc_fd_round, plus E_NOMEM when the round needs more scratch
+ * than the array holds (nothing is enqueued then). */
+#define LDPC_FD_ROUND_SCRATCH_BYTES (64ll * 1024 * 1024)
+int32_t ldpc_fd_round_noalloc(ldpc_fd_code code, int32_t frames, const float *llr, const float *c2v_in,
+                              float *v2c_out, float *c2v_out, uint8_t *hard, uint8_t *fsynd,
+                              uint8_t *synd, int32_t mode, int32_t prec, void *stream);
+
 /* ---- Validation mode: FP64 symbol posteriors ----------------------------------
  * The a-posteriori pmf of every symbol, p_v(x) proportional to the channel pmf
  * times the pmfs of the two check-to-variable messages of v (Sec. 2.1,

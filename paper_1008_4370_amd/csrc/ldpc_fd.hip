@@ -704,9 +704,17 @@ int32_t ldpc_fd_decode_prior(ldpc_fd_code c, int32_t F, const float* prior, int3
                      workspace, workspace_bytes, stream);
 }
 
-int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* c2v_in, float* v2c_out,
-                      float* c2v_out, uint8_t* hard, uint8_t* fsynd, uint8_t* synd, int32_t mode, int32_t prec,
-                      void* stream) {
+}  // extern "C"
+
+// Device scratch of ldpc_fd_round_noalloc (see scratch_for_current_device).
+constexpr size_t kRoundScratchBytes = (size_t)LDPC_FD_ROUND_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kRoundScratchBytes];
+
+namespace {
+
+// Argument checks of ldpc_fd_round and ldpc_fd_round_noalloc.
+int32_t round_check(ldpc_fd_code c, int32_t F, const float* llr, const float* c2v_in, float* v2c_out,
+                    float* c2v_out, uint8_t* hard, uint8_t* fsynd, uint8_t* synd, int32_t mode, int32_t prec) {
   if (!c) return fail(LDPC_FD_E_INVALID, "code is NULL");
   if (F < 0) return fail(LDPC_FD_E_INVALID, "frames < 0");
   if (F == 0) return LDPC_FD_OK;
@@ -722,24 +730,56 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
   if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
   if (mode != LDPC_FD_MODE_FUSED && prec != LDPC_FD_FP32)
     return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN, LOGSP and FSP are FP32 only");
-  hipStream_t s = (hipStream_t)stream;
-  const DevCode& cd = c->dev;
-  char* tmp = nullptr;
-  const size_t n_fsw = align256((size_t)F * c->E), n4 = align256((size_t)F * 4);
+  return LDPC_FD_OK;
+}
+
+// Temporary device memory of one round (decision words, frame flags, 16-bit
+// staging of the imported and exported state, prior factors, round counters).
+struct RoundTmp {
+  uint8_t* fsw;
+  uint32_t *active, *unsat, *mism;
+  int *alist, *nact, *rnd;
+  char *st_in, *st_out;
+  float* prior;
+};
+
+size_t round_layout(const ldpc_fd_code_s* c, int F, int prec, char* base, RoundTmp* t) {
   const size_t n_msg = (size_t)F * c->E * c->q;
-  const size_t n_st = prec == LDPC_FD_FP32 ? 0 : align256(n_msg * 2);
-  const size_t n_pr = align256((size_t)F * c->N * c->m * 4);
-  HIP_TRY(hipMalloc((void**)&tmp, n_fsw + 4 * n4 + 256 + 2 * n_st + n_pr + n4));
-  char* st_in = tmp + n_fsw + 4 * n4 + 256;
-  char* st_out = st_in + n_st;
-  float* prior = (float*)(st_out + n_st);
-  int* rnd = (int*)(tmp + n_fsw + 4 * n4 + 256 + 2 * n_st + n_pr);
-  uint8_t* fsw = (uint8_t*)tmp;
-  uint32_t* active = (uint32_t*)(tmp + n_fsw);
-  uint32_t* unsat = (uint32_t*)(tmp + n_fsw + n4);
-  uint32_t* mism = (uint32_t*)(tmp + n_fsw + 2 * n4);
-  int* alist = (int*)(tmp + n_fsw + 3 * n4);
-  int* nact = (int*)(tmp + n_fsw + 4 * n4);
+  size_t off = 0;
+  auto take = [&](size_t n) { char* p = base ? base + off : nullptr; off += align256(n); return p; };
+  char* fsw = take((size_t)F * c->E);
+  char* act = take((size_t)F * 4);
+  char* uns = take((size_t)F * 4);
+  char* mis = take((size_t)F * 4);
+  char* al = take((size_t)F * 4);
+  char* na = take(16);
+  char* rn = take((size_t)F * 4);
+  char* si = prec == LDPC_FD_FP32 ? nullptr : take(n_msg * 2);
+  char* so = prec == LDPC_FD_FP32 ? nullptr : take(n_msg * 2);
+  char* pr = take((size_t)F * c->N * c->m * 4);
+  if (t)
+    *t = RoundTmp{(uint8_t*)fsw, (uint32_t*)act, (uint32_t*)uns, (uint32_t*)mis, (int*)al, (int*)na, (int*)rn,
+                  si, so, (float*)pr};
+  return off;
+}
+
+// One flooding round (see ldpc_fd_round) with its temporaries carved from
+// `tmp` (round_layout bytes); enqueued on `stream`, not synchronised.
+int32_t round_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* c2v_in, float* v2c_out, float* c2v_out,
+                   uint8_t* hard, uint8_t* fsynd, uint8_t* synd, int32_t mode, int32_t prec, hipStream_t s,
+                   char* tmp) {
+  const DevCode& cd = c->dev;
+  RoundTmp t;
+  round_layout(c, F, prec, tmp, &t);
+  const size_t n_msg = (size_t)F * c->E * c->q;
+  uint8_t* fsw = t.fsw;
+  uint32_t* active = t.active;
+  uint32_t* unsat = t.unsat;
+  uint32_t* mism = t.mism;
+  int* alist = t.alist;
+  int* nact = t.nact;
+  int* rnd = t.rnd;
+  float* prior = t.prior;
   const unsigned fb = cdiv(F, 256);
   hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, active, unsat, mism, alist, nact, (int32_t*)nullptr,
                      (uint32_t*)nullptr, rnd, c2v_in ? 1 : 0);
@@ -778,8 +818,8 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
       S* out = (S*)c2v_out;
       const unsigned g = (unsigned)std::min<size_t>((n_msg / 4 + 255) / 256, 65536);
       if (prec != LDPC_FD_FP32) {
-        in = (S*)st_in;
-        out = (S*)st_out;
+        in = (S*)t.st_in;
+        out = (S*)t.st_out;
         if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, in, n_msg / 4);
       }
       const FusedArgs fa{cd, F, prior, c2v_in ? (void*)out : nullptr, c2v_in ? (void*)in : (void*)out, hard, fsw,
@@ -793,13 +833,72 @@ int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* 
     else run(bf16_t{});
     if (c2v_in) launch_syndrome(c, F, hard, fsw, synd, fsynd, unsat, mism, alist, nact, nullptr, s, rnd);
   }
+  if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+  HIP_TRY(hipGetLastError());
+  return LDPC_FD_OK;
+}
+
+// The scratch array exists once per GPU (each device holds its own copy at its
+// own address until the process ends).  Host code never passes `scratch`
+// itself to a kernel or a copy (in host code the name is a host-side
+// stand-in); it uses the device address that hipGetSymbolAddress returns with
+// the device current, looked up on the first call on each device and kept in
+// g_scratch_ptr.
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+int32_t scratch_for_current_device(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LDPC_FD_E_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(LDPC_FD_E_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LDPC_FD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ldpc_fd_round(ldpc_fd_code c, int32_t F, const float* llr, const float* c2v_in, float* v2c_out,
+                      float* c2v_out, uint8_t* hard, uint8_t* fsynd, uint8_t* synd, int32_t mode, int32_t prec,
+                      void* stream) {
+  int32_t rc = round_check(c, F, llr, c2v_in, v2c_out, c2v_out, hard, fsynd, synd, mode, prec);
+  if (rc || F == 0) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  char* tmp = nullptr;
+  HIP_TRY(hipMalloc((void**)&tmp, round_layout(c, F, prec, nullptr, nullptr)));
+  rc = round_impl(c, F, llr, c2v_in, v2c_out, c2v_out, hard, fsynd, synd, mode, prec, s, tmp);
   hipError_t e1 = hipStreamSynchronize(s);
   hipError_t e2 = hipFree(tmp);
-  if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+  if (rc) return rc;
   if (e1 != hipSuccess) return fail(LDPC_FD_E_HIP, std::string("round: ") + hipGetErrorString(e1));
   if (e2 != hipSuccess) return fail(LDPC_FD_E_HIP, std::string("hipFree: ") + hipGetErrorString(e2));
   return LDPC_FD_OK;
 }
+
+int32_t ldpc_fd_round_noalloc(ldpc_fd_code c, int32_t F, const float* llr, const float* c2v_in, float* v2c_out,
+                              float* c2v_out, uint8_t* hard, uint8_t* fsynd, uint8_t* synd, int32_t mode,
+                              int32_t prec, void* stream) {
+  int32_t rc = round_check(c, F, llr, c2v_in, v2c_out, c2v_out, hard, fsynd, synd, mode, prec);
+  if (rc || F == 0) return rc;
+  const size_t need = round_layout(c, F, prec, nullptr, nullptr);
+  if (need > kRoundScratchBytes)
+    return fail(LDPC_FD_E_NOMEM, "round needs " + std::to_string(need) + " bytes of scratch; the static array holds " +
+                                     std::to_string(kRoundScratchBytes) + " (use fewer frames or ldpc_fd_round)");
+  char* tmp = nullptr;
+  if ((rc = scratch_for_current_device(&tmp))) return rc;
+  return round_impl(c, F, llr, c2v_in, v2c_out, c2v_out, hard, fsynd, synd, mode, prec, (hipStream_t)stream, tmp);
+}
+
 
 int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
   if (!c) return fail(LDPC_FD_E_INVALID, "code is NULL");

@@ -36,6 +36,8 @@ _SIGS = {
                               _c_void_p, _c_void_p, _i64, _c_void_p]),
     "ldpc_fd_round": (_i32, [_c_void_p, _i32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
                              _c_void_p, _i32, _i32, _c_void_p]),
+    "ldpc_fd_round_noalloc": (_i32, [_c_void_p, _i32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                     _c_void_p, _c_void_p, _i32, _i32, _c_void_p]),
     "ldpc_fd_posterior": (_i32, [_c_void_p, _i32, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "ldpc_fd_decode_posterior": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _c_void_p, _c_void_p, _i64, _c_void_p,
                                         _c_void_p]),
@@ -240,6 +242,22 @@ def round_step(code: Code, llr, c2v_in=None, mode: str = "plain", prec: str = "f
     synd = torch.zeros((F, code.M), dtype=torch.uint8, device=dev)
     _check(lib().ldpc_fd_round(code.handle, F, _ptr(llr), _ptr(c2v_in), _ptr(v2c_out), _ptr(c2v_out),
                                _ptr(hard), _ptr(fsynd), _ptr(synd), MODE[mode], PREC[prec], _stream()))
+    return dict(c2v=c2v_out, v2c=v2c_out, hard=hard, fsynd=fsynd, synd=synd)
+
+
+def round_step_noalloc(code: Code, llr, c2v_in=None, mode: str = "plain", prec: str = "fp32"):
+    """ldpc_fd_round_noalloc: the same round with the library's static scratch
+    (no device allocation inside the call, no synchronisation)."""
+    import torch
+    F = llr.shape[0]
+    dev = llr.device
+    c2v_out = torch.empty((F, code.E, code.q), dtype=torch.float32, device=dev)
+    v2c_out = torch.empty_like(c2v_out) if mode != "fused" else None
+    hard = torch.zeros((F, code.N), dtype=torch.uint8, device=dev)
+    fsynd = torch.zeros((F, code.M), dtype=torch.uint8, device=dev)
+    synd = torch.zeros((F, code.M), dtype=torch.uint8, device=dev)
+    _check(lib().ldpc_fd_round_noalloc(code.handle, F, _ptr(llr), _ptr(c2v_in), _ptr(v2c_out), _ptr(c2v_out),
+                                       _ptr(hard), _ptr(fsynd), _ptr(synd), MODE[mode], PREC[prec], _stream()))
     return dict(c2v=c2v_out, v2c=v2c_out, hard=hard, fsynd=fsynd, synd=synd)
 
 
