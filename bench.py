@@ -7,9 +7,12 @@ max 100 rounds, stop at zero syndrome.  One step = one complete decode of the
 4096-frame batch (every round until every frame has stopped), with the LLRs
 already resident in HBM.
 
-Prints one JSON line.  `roofline` is measured live for the fused pass kernel
-(HIP events around each launch on the decode stream): algorithmic bytes per
-frame-round B = (2E+N)*q*s + 4*N*m (s = bytes per stored message entry), plus
+Prints one JSON line.  `value` comes from the timed decodes as the library
+runs them (graph replay of chunks of rounds).  `roofline` is measured live for
+the fused pass kernel over as many further decodes of the same batch with HIP
+events around each launch on the decode stream (eager launches, since kernels
+inside a replayed graph cannot be timed): algorithmic bytes per frame-round
+B = (2E+N)*q*s + 4*N*m (s = bytes per stored message entry), plus
 E*q*s + 4*N*m for the first pass of each frame.  `cpu_baseline` times the FP64
 oracle on a bounded sample of the same frames on the host cores.
 """
@@ -38,10 +41,21 @@ def _oracle_worker(args):
     return idx, time.perf_counter() - t0, r.hard, r.iters
 
 
+def host_cores():
+    """Host cores this process may use: the affinity mask, capped at 16 (the
+    host CPU share that goes with one GPU on the measurement machines, whatever
+    the machine's total core count)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(batch, max_iter, frames_per_worker=2, workers=None):
     """Time the FP64 oracle (never tuned) on a sample of the batch's frames."""
     import multiprocessing as mp
-    workers = workers or min(16, os.cpu_count() or 1)
+    workers = workers or host_cores()
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[k] = "1"
     c = batch.code
@@ -58,10 +72,23 @@ def cpu_baseline(batch, max_iter, frames_per_worker=2, workers=None):
     mbps = frames * batch.info_bits_per_frame / wall / 1e6
     return dict(value=mbps, unit="Mbit/s", cores=workers, kind="oracle",
                 sample=f"{frames} frames (evenly spaced over the batch), full decode to the same stop rule, "
-                       f"{workers} processes x 1 thread, {wall:.1f} s wall"), res
+                       f"{workers} processes x 1 thread (all of the host share), {wall:.1f} s wall"), res
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_fused_gf64_n1000_fp32_traffic.json")
+def oracle_agreement(res, hard, iters):
+    """Per-frame agreement of a GPU decode with the oracle sample: frames whose
+    hard decisions and stopping round are both identical."""
+    idx = np.concatenate([r[0] for r in res])
+    ohard = np.concatenate([r[2] for r in res])
+    oiters = np.concatenate([r[3] for r in res])
+    same = np.all(hard[idx] == ohard, axis=1) & (iters[idx] == oiters)
+    return {"frames": int(len(idx)), "identical": int(same.sum()), "fraction": round(float(same.mean()), 4)}
+
+
+def traffic_profile(prec):
+    """Committed FETCH_SIZE / WRITE_SIZE record of the headline workload's fused
+    pass at storage type prec."""
+    return os.path.join(ROOT, "profiles", f"k_fused_gf64_n1000_{prec}_traffic.json")
 
 
 def source_sha256():
@@ -77,25 +104,83 @@ def source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(prec):
     """HBM bytes per k_fused launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (copy-calibrated), or None when the library sources have
-    changed since they were taken."""
-    if not os.path.exists(TRAFFIC_PROFILE):
+    WRITE_SIZE runs (copy-calibrated), or None when there are none for prec or
+    the library sources have changed since they were taken."""
+    path = traffic_profile(prec)
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_PROFILE) as fh:
+    with open(path) as fh:
         t = json.load(fh)
     if t.get("source_sha256") != source_sha256():
         return None
     return t
 
 
+BYTES_FORMULA = ("B = (2E+N)*q*s + 4*N*m per frame-round (read the other-check and own messages, write the new "
+                 "state, read the LLRs) for each of a frame's iters rounds, plus E*q*s + 4*N*m for its first pass "
+                 "(round 0 -> 1 writes the state, reads the LLRs)")
+
+
 def alg_bytes(code, iters, s, first_pass=True):
     """Algorithmic HBM bytes of all fused-pass launches for one decode."""
     E, N, q, m = code.E, code.N, code.q, code.m
     per_round = (2 * E + N) * q * s + 4 * N * m
-    first = E * q * s + 4 * N * m
+    first = E * q * s + 4 * N * m if first_pass else 0
     return int(len(iters) * first + int(np.sum(iters)) * per_round)
+
+
+def time_leg(batch, llr, prec, mode, steps, max_iter, precise=None, lane_entries=None):
+    """Another decoder over the same resident batch (its own code object, the
+    autotuned launch choices of that storage type, optionally another
+    variable-node form): Mbit/s, FER, mean rounds and the roofline fraction of
+    its per-round kernels under its own storage bytes (FUSED: the fused pass;
+    PLAIN: check plus variable kernels, each moving 2 E q 4 bytes per
+    frame-round)."""
+    import torch
+    from paper_1008_4370_amd import autotune
+    from paper_1008_4370_amd import decoder as D
+    F = batch.llr.shape[0]
+    code = D.Code.from_synth(batch.code)
+    if mode == "fused":
+        autotune.apply(code, prec, F)
+    if precise is not None:
+        code.set_tuning(precise=precise)
+    if lane_entries:
+        code.set_tuning(lane_entries=lane_entries)
+    dec = D.Decoder(code, F, prec, mode)
+    dec(llr, max_iter)
+    torch.cuda.synchronize()
+    for k in (D.K_FUSED, D.K_CHECK, D.K_VAR):
+        D.profile_read(k)
+    D.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = dec(llr, max_iter)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    D.profile_enable(False)
+    kf, _ = D.profile_read(D.K_FUSED)
+    kc, _ = D.profile_read(D.K_CHECK)
+    kv, _ = D.profile_read(D.K_VAR)
+    hard = out["hard"].cpu().numpy()
+    iters = out["iters"].cpu().numpy()
+    s = 4 if prec == "fp32" else 2
+    if mode == "fused":
+        kms = kf
+        nbytes = alg_bytes(batch.code, iters, s) * steps
+    else:
+        kms = kc + kv
+        nbytes = int(np.sum(iters)) * 4 * batch.code.E * batch.code.q * 4 * steps
+    form = code.get_tuning()["precise"]
+    code.close()
+    leg = {"storage": prec, "mode": mode, "precise": form, "ms_per_step": round(ms, 4),
+           "value": round(F * batch.info_bits_per_frame / (ms / 1e3) / 1e6, 3),
+           "fer": float(np.any(hard != batch.cw, axis=1).mean()), "mean_iters": float(iters.mean()),
+           "kernel_ms_per_step": round(kms / steps, 4),
+           "roofline_frac": round(nbytes / (kms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if kms > 0 else None}
+    return leg, hard, iters
 
 
 C4_MIX = ("gf16_n2048", "gf64_n512", "gf256_n256_k16")
@@ -115,7 +200,9 @@ def run_mixed(args):
     tuned = [autotune.apply(c, args.prec, b.llr.shape[0]) is not None for c, b in zip(codes, batches)]
     llrs = [torch.from_numpy(b.llr).cuda() for b in batches]
     pool = D.Pool(codes, [b.llr.shape[0] for b in batches], prec=args.prec)
-    chunk = args.chunk or 4
+    # default: one pool step of max_iter + 1 passes (one graph launch, no host
+    # read); --chunk c: steps of c passes with host reads in between
+    chunk = args.chunk or None
     for _ in range(args.warmup):
         serving.decode_mixed(pool, llrs, args.max_iter, chunk)
     torch.cuda.synchronize()
@@ -148,7 +235,9 @@ def run_mixed(args):
         "warmup": args.warmup, "ms_per_step": round(ms_mix, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "3000 x GF(16)(2,4) N=2048 + 6000 x GF(64)(2,6) N=512 + 2000 x GF(256)(2,16) "
-                               f"N=256, 2.5 dB, max {args.max_iter} rounds, one pool, {chunk} passes per replay",
+                               f"N=256, 2.5 dB, max {args.max_iter} rounds, one pool, "
+                               + (f"{chunk} passes per step" if chunk else
+                                  f"one step of {args.max_iter + 1} passes (one graph launch)"),
                    "storage": args.prec, "parallelism": "1 GPU"},
         "sequential_ms_per_step": round(ms_seq, 4),
         "sequential_mbps": round(bits / (ms_seq / 1e3) / 1e6, 3),
@@ -202,7 +291,7 @@ def main():
     ap.add_argument("--point", type=int, default=None,
                     help="Eb/N0 index into the workload's list (default: its 2.5 dB point, else its first)")
     ap.add_argument("--prec", default=None, choices=["fp32", "fp16", "bf16"],
-                    help="message storage (default fp32; fp16 for the serving workload)")
+                    help="message storage (default fp16; fp32 for the mixed workload)")
     ap.add_argument("--mode", default="fused", choices=["fused", "plain"])
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -211,8 +300,7 @@ def main():
     ap.add_argument("--grid-blocks", type=int, default=0, help="fused-pass grid (0 = library default)")
     ap.add_argument("--chunk", type=int, default=0, help="rounds between host checks (0 = default)")
     ap.add_argument("--no-kernel-timing", action="store_true",
-                    help="time steps without per-kernel HIP events (lets the decoder replay graphs); "
-                         "roofline is then omitted")
+                    help="skip the decodes with HIP events around every kernel launch; roofline is then omitted")
     ap.add_argument("--graphs", type=int, default=-1, help="1/0: replay captured round chunks (-1 = default)")
     ap.add_argument("--serve-load", type=float, default=100000.0,
                     help="offered frames/s of the serving phase that measures p50/p99 frame latency (0 = skip)")
@@ -223,6 +311,8 @@ def main():
                     help="skip timing the conventional log-domain SP decoder on the same batch")
     ap.add_argument("--no-precise-variant", action="store_true",
                     help="skip the extra timing of the FP64 variable node")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the other storage type's and the PLAIN FP32 decoder's timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (calibrates rocprofv3 "
                          "FETCH_SIZE/WRITE_SIZE against a known byte count) and exit")
@@ -243,7 +333,9 @@ def main():
         sys.exit(2)
 
     if args.prec is None:
-        args.prec = "fp16" if args.workload == "serving" else "fp32"
+        # 16-bit message storage (pmf words) decodes at the FP32 frame error
+        # rate in fewer bytes; the uneven batch is specified with FP32 messages
+        args.prec = "fp32" if args.workload == "mixed" else "fp16"
     if args.workload == "mixed":
         return run_mixed(args)
     if args.workload == "serving":
@@ -254,10 +346,10 @@ def main():
         args.point = pts.index(2.5) if 2.5 in pts else 0
     batch = synth.make_batch(args.workload, point=args.point)
     F = batch.llr.shape[0]
-    cpu = None
+    cpu, cpu_res = None, None
     if not args.no_cpu_baseline:
         print("[bench] cpu_baseline: FP64 oracle on a sample ...", file=sys.stderr, flush=True)
-        cpu, _ = cpu_baseline(batch, args.max_iter, args.cpu_frames_per_worker)
+        cpu, cpu_res = cpu_baseline(batch, args.max_iter, args.cpu_frames_per_worker)
         print(f"[bench] cpu_baseline done: {cpu['value']:.4f} Mbit/s", file=sys.stderr, flush=True)
 
     import torch
@@ -279,68 +371,45 @@ def main():
         dec(llr, args.max_iter)
     torch.cuda.synchronize()
     kernel = D.K_FUSED if args.mode == "fused" else D.K_CHECK
-    D.profile_read(D.K_FUSED), D.profile_read(D.K_CHECK), D.profile_read(D.K_VAR)
-    D.profile_enable(not args.no_kernel_timing)
+    # The timed steps run as the decoder runs in production (captured chunks
+    # of rounds replayed as graphs, where the library uses them).
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out = dec(llr, args.max_iter)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    D.profile_enable(False)
-    kms, launches = D.profile_read(kernel)
-    ms_var, launches_var = D.profile_read(D.K_VAR)
     ms_step = (t1 - t0) / args.steps * 1e3
-
-    precise_line = None
-    if args.mode == "fused" and not args.precise and not args.no_precise_variant:
-        # The same batch with the FP64 variable node (tuning key PRECISE), for
-        # the throughput / frame-error trade-off; not the headline value.
-        before = code.get_tuning()
-        # FP64 registers: 8 entries per lane where the code has that variant
-        if code.kmax <= 8 and code.m >= 3:
-            code.set_tuning(lane_entries=8)
-        code.set_tuning(precise=1)
-        pdec = D.Decoder(code, F, args.prec, args.mode)
-        pdec(llr, args.max_iter)
-        torch.cuda.synchronize()
-        tp0 = time.perf_counter()
+    # Kernel durations: the same steps again with a pair of HIP events on the
+    # decode stream around every launch of the per-round kernels (HIP cannot
+    # time kernels inside a replayed graph, so these decodes launch every pass
+    # from the host; the kernels and their results are the same).
+    kms, launches, ms_var, ms_step_events = 0.0, 0, 0.0, None
+    if not args.no_kernel_timing:
+        D.profile_read(D.K_FUSED), D.profile_read(D.K_CHECK), D.profile_read(D.K_VAR)
+        D.profile_enable(True)
+        te0 = time.perf_counter()
         for _ in range(args.steps):
-            pout = pdec(llr, args.max_iter)
+            dec(llr, args.max_iter)
         torch.cuda.synchronize()
-        pms = (time.perf_counter() - tp0) / args.steps * 1e3
-        phard = pout["hard"].cpu().numpy()
-        precise_line = {"ms_per_step": round(pms, 4),
-                        "value": round(F * batch.info_bits_per_frame / (pms / 1e3) / 1e6, 3),
-                        "fer": float(np.any(phard != batch.cw, axis=1).mean()),
-                        "tuning": code.get_tuning()}
-        code.set_tuning(**before)
-        del pdec
+        ms_step_events = (time.perf_counter() - te0) / args.steps * 1e3
+        D.profile_enable(False)
+        kms, launches = D.profile_read(kernel)
+        ms_var, _ = D.profile_read(D.K_VAR)
 
-    prob_line = None
+    precise_line = prob_line = None
     if args.mode == "fused" and not args.precise and not args.no_precise_variant:
-        # The same batch with the FP32 butterfly variable node (tuning key
-        # PRECISE = 0: prior convolution as m butterflies with tanh(L/2)
-        # factors); same tuned launch choices as the headline.
-        before = code.get_tuning()
-        code.set_tuning(precise=0)
-        qdec = D.Decoder(code, F, args.prec, args.mode)
-        qdec(llr, args.max_iter)
-        torch.cuda.synchronize()
-        tq0 = time.perf_counter()
-        for _ in range(args.steps):
-            qout = qdec(llr, args.max_iter)
-        torch.cuda.synchronize()
-        qms = (time.perf_counter() - tq0) / args.steps * 1e3
-        qhard = qout["hard"].cpu().numpy()
-        prob_line = {"ms_per_step": round(qms, 4),
-                     "value": round(F * batch.info_bits_per_frame / (qms / 1e3) / 1e6, 3),
-                     "fer": float(np.any(qhard != batch.cw, axis=1).mean())}
-        code.set_tuning(**before)
-        del qdec
+        # The same batch with the other FP32 variable-node forms (FP32 storage;
+        # 16-bit pmf words are read by the default form only): the FP64
+        # variable node (tuning key PRECISE = 1, 8 entries per lane where the
+        # code has that variant) and the FP32 butterfly form (PRECISE = 0).
+        lane = 8 if code.kmax <= 8 and code.m >= 3 else None
+        precise_line, _, _ = time_leg(batch, llr, "fp32", "fused", args.steps, args.max_iter, precise=1,
+                                      lane_entries=lane)
+        prob_line, _, _ = time_leg(batch, llr, "fp32", "fused", args.steps, args.max_iter, precise=0)
 
     logsp_line = None
-    if args.mode == "fused" and args.prec == "fp32" and not args.no_logsp_variant:
+    if args.mode == "fused" and not args.no_logsp_variant:
         # The same batch through the conventional log-domain SP decoder (the
         # comparison of Table 1): whole-decode time, and the time of its check
         # and variable kernels per frame-round next to the fused pass's.
@@ -370,6 +439,22 @@ def main():
                       "lfsp_speedup": round(lms / ms_step, 3)}
         del ldec
 
+    legs = None
+    if args.mode == "fused" and not args.precise and not args.no_legs:
+        # The comparison the precision plan sets: the 16-bit-storage decoder
+        # against the FP32 decoders on the same frames (the other storage type
+        # of the fused decoder, and the PLAIN two-kernel FP32 decoder).
+        legs = {}
+        other = "fp16" if args.prec == "fp32" else "fp32"
+        legs[other], lh, li = time_leg(batch, llr, other, "fused", args.steps, args.max_iter)
+        if cpu_res is not None:
+            legs[other]["oracle_agreement"] = oracle_agreement(cpu_res, lh, li)
+        legs["plain_fp32"], lh, li = time_leg(batch, llr, "fp32", "plain", args.steps, args.max_iter)
+        if cpu_res is not None:
+            legs["plain_fp32"]["oracle_agreement"] = oracle_agreement(cpu_res, lh, li)
+        print(f"[bench] legs: " + ", ".join(f"{k} {v['value']:.1f} Mbit/s FER {v['fer']:.2e}"
+                                             for k, v in legs.items()), file=sys.stderr, flush=True)
+
     serve = None
     if args.serve_load > 0:
         # Continuous batching of the same frames arriving as a Poisson process
@@ -392,11 +477,14 @@ def main():
     frame_err = np.any(hard != batch.cw, axis=1)
     bit_err = int(np.sum((((hard.astype(np.int64) ^ batch.cw)[..., None] >> np.arange(batch.code.m)) & 1)))
     s = 4 if args.prec == "fp32" else 2
+    achieved_rounds = None
     if kms <= 0:
         achieved, roof_kernel = None, None
     elif args.mode == "fused":
         total_bytes = alg_bytes(batch.code, iters, s) * args.steps
         achieved = total_bytes / (kms / 1e3) / 1e9
+        # the same kernel time over iters x B alone (first passes not counted)
+        achieved_rounds = alg_bytes(batch.code, iters, s, first_pass=False) * args.steps / (kms / 1e3) / 1e9
         roof_kernel = "k_fused"
     else:
         # PLAIN: check + variable kernels each move 2*E*q*4 bytes per frame-round
@@ -407,11 +495,11 @@ def main():
     # measured HBM bytes per k_fused launch (committed counters) for this exact
     # configuration: default workload, FP32 storage, fused, tuned defaults
     traffic, traffic_note = None, "no counters for this configuration"
-    if (args.workload == "gf64_n1000" and args.prec == "fp32" and args.mode == "fused" and not args.precise
+    if (args.workload == "gf64_n1000" and args.mode == "fused" and not args.precise
             and not tune and args.point == 2 and args.max_iter == 100):
-        t = measured_traffic()
+        t = measured_traffic(args.prec)
         if t is None:
-            traffic_note = "kernel sources changed since the counters were taken"
+            traffic_note = "no counters for the current kernel sources"
         else:
             traffic = int(round(t["traffic_bytes_per_launch"]))
             traffic_note = (f"HBM bytes per launch from FETCH_SIZE x {t['fetch_factor']:.3f} + WRITE_SIZE x "
@@ -451,10 +539,15 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "bytes": BYTES_FORMULA if args.mode == "fused" else "4*E*q*4 per frame-round (check + variable kernels)",
+            "frac_rounds_only": None if achieved_rounds is None else round(achieved_rounds / HBM_PEAK_GBS, 4),
             "launches": int(launches),
             "kernel_ms_per_step": round(kms / args.steps, 4),
+            "timing": f"HIP events around every launch over {args.steps} further decodes of the same batch "
+                      f"(eager launches: {ms_step_events:.3f} ms per decode)" if ms_step_events else None,
         },
-        "cpu_baseline": cpu,
+        "cpu_baseline": None if cpu is None else dict(cpu, agreement=oracle_agreement(cpu_res, hard, iters)),
+        "legs": legs,
         "precise_variant": precise_line,
         "butterfly_variant": prob_line,
         "logsp_variant": logsp_line,

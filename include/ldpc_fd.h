@@ -29,6 +29,13 @@
  *   stored as one float per entry whose sign bit is the GF(2) sign and whose
  *   magnitude is -log2|P_cv(z)| in [0, 100] (base 2 instead of the paper's
  *   natural log; a positive rescaling).  Layout [frames][E][2^m] contiguous.
+ *   With 16-bit storage (LDPC_FD_FP16, LDPC_FD_BF16) the FUSED decoder keeps
+ *   each message as q times its pmf instead, q p_cv(x) = sum_z P_cv(z)
+ *   (-1)^(x.z) clamped at zero (in [0, q]), rounded to the storage type: a
+ *   16-bit float keeps every probability to a relative 2^-11 (FP16) or 2^-8
+ *   (BF16), where a 16-bit signed-log Fourier word would carry P(z) only to
+ *   an absolute ~1e-4.  Entry points that import or export a state always use
+ *   the FP32 signed-log layout above.
  * Errors: every function returns LDPC_FD_OK (0) or a negative code; no
  *   exception crosses the ABI.  ldpc_fd_last_error() gives a message for the
  *   last failure on the calling thread.
@@ -179,10 +186,13 @@ int32_t ldpc_fd_decode_prior(ldpc_fd_code code, int32_t frames, const float *pri
  *   layout.  mode selects which kernels compute it (PLAIN or FUSED; LOGSP
  *   instead takes and writes log2 pmfs [frames][E][2^m] with maximum 0 in
  *   c2v_in, v2c_out and c2v_out, v2c_out required).  prec
- *   selects the storage type the FUSED pass reads and writes: the imported
- *   state is rounded to it first and the result widened back to FP32, so the
- *   difference to an FP32 round is the one-round storage error (PLAIN: FP32
- *   only).  The call allocates temporary device memory and synchronises.
+ *   selects the storage type the FUSED pass reads and writes: with 16-bit
+ *   storage the imported state is converted to the stored words first (q
+ *   times the pmf, transformed in FP64, clamped at zero, rounded) and the
+ *   stored result converted back to FP32 signed-log words normalised to
+ *   P(0) = 1, so the difference to an FP32 round is the one-round storage
+ *   error (PLAIN: FP32 only).  The call allocates temporary device memory and
+ *   synchronises.
  * Errors: E_INVALID, E_UNSUPPORTED (PLAIN or LOGSP with prec != FP32), E_HIP. */
 int32_t ldpc_fd_round(ldpc_fd_code code, int32_t frames, const float *llr, const float *c2v_in,
                       float *v2c_out, float *c2v_out, uint8_t *hard, uint8_t *fsynd,
@@ -207,6 +217,57 @@ int32_t ldpc_fd_round(ldpc_fd_code code, int32_t frames, const float *llr, const
 int32_t ldpc_fd_round_noalloc(ldpc_fd_code code, int32_t frames, const float *llr, const float *c2v_in,
                               float *v2c_out, float *c2v_out, uint8_t *hard, uint8_t *fsynd,
                               uint8_t *synd, int32_t mode, int32_t prec, void *stream);
+
+/* ---- Decode with an argument struct and flags ---------------------------------
+ * The same decode as ldpc_fd_decode (Sec. 3.2 with the stopping rule of Sec. 2)
+ * with its arguments in one struct and these flags:
+ *   LDPC_FD_FLAG_NO_EARLY_STOP: every frame runs max_iter rounds whatever its
+ *     syndromes; iters = max_iter, hard/synd are the last round's, and the
+ *     converged status bit reports whether that last decision passed the
+ *     codeword test (the mismatch bit still accumulates over all rounds).
+ *   LDPC_FD_FLAG_VALIDATION (FUSED only): also write posterior[frames][N][2^m]
+ *     (device double), the FP64 posterior of every frame at its stopping
+ *     round (as ldpc_fd_decode_posterior).
+ *   LDPC_FD_FLAG_ASYNC (FUSED and PLAIN with column weight 2 only): the call
+ *     enqueues every round on the stream and returns without synchronising
+ *     with it (no read of the active-frame count): max_iter + 1 passes are
+ *     enqueued, the passes after the last frame has stopped find no active
+ *     frame, and the few-frames variant is not used.  Results are the same.
+ * Without ASYNC the call synchronises with the stream to read the count of
+ * active frames between chunks of rounds (as ldpc_fd_decode).
+ * Errors: as ldpc_fd_decode; E_INVALID for unknown flag bits or VALIDATION
+ *   without a posterior buffer; E_UNSUPPORTED for VALIDATION outside FUSED
+ *   mode or ASYNC with the LOGSP, FSP or irregular PLAIN decoders. */
+#define LDPC_FD_FLAG_NO_EARLY_STOP 1u
+#define LDPC_FD_FLAG_VALIDATION 2u
+#define LDPC_FD_FLAG_ASYNC 4u
+typedef struct {
+  int32_t frames, max_iter, prec, mode;
+  uint32_t flags;
+  const float *llr;        /* device [frames][N][m] */
+  uint8_t *hard;           /* device [frames][N] */
+  uint8_t *synd;           /* device [frames][M] */
+  int32_t *iters;          /* device [frames] */
+  uint32_t *status;        /* device [frames] */
+  double *posterior;       /* device [frames][N][2^m] or NULL (VALIDATION only) */
+  void *workspace;         /* device, ldpc_fd_workspace_bytes(frames, prec, mode) */
+  int64_t workspace_bytes;
+} ldpc_fd_decode_args;
+int32_t ldpc_fd_decode_ex(ldpc_fd_code code, const ldpc_fd_decode_args *args, void *stream);
+
+/* `rounds` flooding rounds from an imported state (several ldpc_fd_round
+ * steps in one call): on entry c2v_inout holds Lambda_cv^(l) in the FP32
+ * message layout (ignored when from_channel != 0: the rounds then start at
+ * round 0 from the channel prior), on return Lambda_cv^(l + rounds).  hard,
+ * fsynd and synd receive the tentative decision of the last round that formed
+ * one (round l + rounds - 1; none when from_channel and rounds == 1, then they
+ * may be NULL).  No stopping rule is applied.  mode and prec as
+ * ldpc_fd_round (16-bit storage: each round's state is rounded to the stored
+ * word).  The call allocates temporary device memory and synchronises.
+ * Errors: as ldpc_fd_round; E_INVALID for rounds outside 1..100000. */
+int32_t ldpc_fd_run_rounds(ldpc_fd_code code, int32_t frames, const float *llr, int32_t rounds,
+                           int32_t from_channel, float *c2v_inout, uint8_t *hard, uint8_t *fsynd,
+                           uint8_t *synd, int32_t mode, int32_t prec, void *stream);
 
 /* ---- Validation mode: FP64 symbol posteriors ----------------------------------
  * The a-posteriori pmf of every symbol, p_v(x) proportional to the channel pmf
@@ -267,6 +328,14 @@ int32_t ldpc_fd_pool_slot_bytes(ldpc_fd_code code, int32_t prec, int64_t *bytes)
  * Errors: E_INVALID, E_NOMEM (device or pinned-host allocation), E_HIP. */
 int32_t ldpc_fd_pool_create(const ldpc_fd_code *codes, int32_t ncodes, const int32_t *slots, int32_t prec,
                             void *stream, ldpc_fd_pool *out);
+
+/* A pool whose slot counts come from an HBM budget: each code gets an equal
+ * share of hbm_budget bytes, divided by its ldpc_fd_pool_slot_bytes at prec
+ * (at least one slot, at most 2^22; ldpc_fd_pool_free_slots reports the
+ * counts).  Errors: as ldpc_fd_pool_create; E_NOMEM when a code's share holds
+ * no slot. */
+int32_t ldpc_fd_pool_create_budget(const ldpc_fd_code *codes, int32_t ncodes, int64_t hbm_budget, int32_t prec,
+                                   void *stream, ldpc_fd_pool *out);
 
 /* Synchronise the pool's stream and free all its resources (NULL: no-op). */
 int32_t ldpc_fd_pool_destroy(ldpc_fd_pool pool);
@@ -330,8 +399,10 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *     differences from certainty that decide messages where the channel and
  *     the check messages disagree: GF(64) N=1000 at 2.5 dB, FER 3.2e-3 vs
  *     1.0e-3); 1 = the butterflies in FP64 from the stored words, with 1 - |P|
- *     and 1 - |tanh(L/2)| carried at FP32 relative precision (not built for
- *     BF16 storage: decode, round and pool creation return E_UNSUPPORTED).
+ *     and 1 - |tanh(L/2)| carried at FP32 relative precision.  16-bit
+ *     storage (pmf words) is built for the default form only: with PRECISE
+ *     0 or 1 and FP16/BF16, decode, round and pool creation return
+ *     E_UNSUPPORTED.
  *     Unlike the other keys this one changes results.  A pool uses the
  *     setting its codes had when it was created.
  *   LDPC_FD_TUNE_DECISION_MFMA (with PRECISE = 0 only): 1 = the three Hadamard transforms of the

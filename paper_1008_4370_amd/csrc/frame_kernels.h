@@ -139,13 +139,65 @@ __global__ __launch_bounds__(256) void k_syndrome_frames(DevCode cd, const uint8
                        s_exp, s_log);
 }
 
-// Elementwise conversion between message storage types (n4 groups of 4).
-template <typename Sin, typename Sout>
-__global__ void k_convert(const Sin* __restrict__ in, Sout* __restrict__ out, size_t n4) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
-    float v[4];
-    IO<Sin>::load4(in + 4 * i, v);
-    IO<Sout>::store4(out + 4 * i, v);
+// In-place Hadamard transform of a length-q FP64 vector in LDS by q/2 or
+// more threads (q <= blockDim.x).
+__device__ __forceinline__ void lds_wht_d(double* a, int q) {
+  const int z = threadIdx.x;
+  for (int s = 1; s < q; s <<= 1) {
+    if (z < q / 2) {
+      const int lo = (z / s) * 2 * s + (z % s), hi = lo + s;
+      const double a0 = a[lo], a1 = a[hi];
+      a[lo] = a0 + a1;
+      a[hi] = a0 - a1;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ float load_pmf_word(_Float16 w) { return (float)w; }
+__device__ __forceinline__ float load_pmf_word(bf16_t w) { return __uint_as_float((uint32_t)w.bits << 16); }
+__device__ __forceinline__ void store_pmf_word(_Float16* p, float v) { *p = (_Float16)v; }
+__device__ __forceinline__ void store_pmf_word(bf16_t* p, float v) { p->bits = (uint16_t)f32_to_bf16_rne(v); }
+
+// Signed-log message vectors [nvec][q] (FP32 layout) -> 16-bit pmf words:
+// P(z) = sign 2^-|w| in FP64, q p(x) = sum_z P(z) (-1)^(x.z), clamped at zero,
+// rounded to FP32 and then to the storage type.
+template <typename S>
+__global__ void k_lambda_to_pmf(const float* __restrict__ in, S* __restrict__ out, long nvec, int q) {
+  extern __shared__ double shd[];
+  const int z = threadIdx.x;
+  for (long i = blockIdx.x; i < nvec; i += gridDim.x) {
+    if (z < q) {
+      const float w = in[i * q + z];
+      const double a = exp2(-(double)__builtin_fabsf(w));
+      shd[z] = (__float_as_uint(w) & 0x80000000u) ? -a : a;
+    }
+    __syncthreads();
+    lds_wht_d(shd, q);
+    if (z < q) store_pmf_word(out + i * q + z, (float)(shd[z] > 0.0 ? shd[z] : 0.0));
+    __syncthreads();  // shd is rewritten by the next vector
+  }
+}
+
+// 16-bit pmf words [nvec][q] -> signed-log FP32 words of the same message,
+// normalised to P(0) = 1: Q(z) = sum_x (q p(x)) (-1)^(x.z) in FP64, word =
+// sign | min(-log2 |Q(z) / Q(0)|, kLmax).
+template <typename S>
+__global__ void k_pmf_to_lambda(const S* __restrict__ in, float* __restrict__ out, long nvec, int q) {
+  extern __shared__ double shd[];
+  const int z = threadIdx.x;
+  for (long i = blockIdx.x; i < nvec; i += gridDim.x) {
+    if (z < q) shd[z] = (double)load_pmf_word(in[i * q + z]);
+    __syncthreads();
+    lds_wht_d(shd, q);
+    if (z < q) {
+      const double q0 = shd[0] > 0.0 ? shd[0] : 1e-300;
+      const double r = shd[z] / q0;
+      const double mag = __builtin_fmin(__builtin_fmax(-log2(__builtin_fabs(r)), 0.0), (double)kLmax);
+      const float fm = (float)mag;
+      out[i * q + z] = r < 0.0 ? -fm : fm;
+    }
+    __syncthreads();
   }
 }
 
@@ -170,13 +222,16 @@ __global__ void k_init_frames(int F, uint32_t* active, uint32_t* unsat, uint32_t
 
 // PLAIN and LOGSP decoders: stopping rule for round ell over all frames; with
 // alist, the frames that continue are appended to it (in counter order).
+// early_stop = 0: frames run to max_iter whatever their syndromes (the
+// converged bit then reports the last round's codeword test).
 __global__ void k_retire_plain(int F, int ell, int max_iter, uint32_t* active, uint32_t* unsat,
-                               uint32_t* mism, int32_t* iters, uint32_t* status, uint32_t* count, int* alist) {
+                               uint32_t* mism, int32_t* iters, uint32_t* status, uint32_t* count, int* alist,
+                               int early_stop) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F || !active[f]) return;
   iters[f] = ell;
   uint32_t st = status[f] | (mism[f] ? 2u : 0u);
-  if (!unsat[f]) {
+  if (!unsat[f] && (early_stop || ell >= max_iter)) {
     st |= 1u;
     active[f] = 0u;
   } else if (ell >= max_iter) {
@@ -193,14 +248,15 @@ __global__ void k_retire_plain(int F, int ell, int max_iter, uint32_t* active, u
 // FUSED decoder: stopping rule and stable compaction of the active list by one
 // workgroup of NT threads.  For each active frame with l = rnd[f] >= 1 the
 // decision of round l was formed in the pass: iters = l; the frame stops when
-// both syndromes were zero, or fails at l = max_iter.  Continuing frames
-// advance rnd.  Stopped frames are appended to `done` (when given) for
-// harvesting.
+// both syndromes were zero (unless early_stop = 0), or at l = max_iter, with
+// the converged bit set when its last decision passed the codeword test.
+// Continuing frames advance rnd.  Stopped frames are appended to `done` (when
+// given) for harvesting.
 template <int NT>
-__device__ __forceinline__ void retire_compact_body(int maxit_all, const int* __restrict__ maxit, int* alist,
-                                                    int* tmp, int* nact_p, uint32_t* unsat, uint32_t* mism,
-                                                    int32_t* iters, uint32_t* status, int* rnd, int* done,
-                                                    int* ndone, int* wsum, int* base_s) {
+__device__ __forceinline__ void retire_compact_body(int maxit_all, const int* __restrict__ maxit, int early_stop,
+                                                    int* alist, int* tmp, int* nact_p, uint32_t* unsat,
+                                                    uint32_t* mism, int32_t* iters, uint32_t* status, int* rnd,
+                                                    int* done, int* ndone, int* wsum, int* base_s) {
   constexpr int NW = NT / 64;
   const int nact = *nact_p;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -216,11 +272,12 @@ __device__ __forceinline__ void retire_compact_body(int maxit_all, const int* __
         iters[f] = ell;
         uint32_t st = status[f] | (mism[f] ? 2u : 0u);
         const bool conv = !unsat[f];
-        if (conv) st |= 1u;
+        const bool more = ell < (maxit ? maxit[f] : maxit_all);
+        keep = more && !(conv && early_stop);
+        if (conv && !keep) st |= 1u;
         status[f] = st;
         unsat[f] = 0u;
         mism[f] = 0u;
-        keep = !conv && ell < (maxit ? maxit[f] : maxit_all);
       } else {
         keep = 1;
       }
@@ -250,14 +307,14 @@ __device__ __forceinline__ void retire_compact_body(int maxit_all, const int* __
 }
 
 // The same as a kernel of one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_retire_compact(int maxit_all, const int* __restrict__ maxit, int* alist,
-                                                         int* tmp, int* nact_p, uint32_t* unsat, uint32_t* mism,
-                                                         int32_t* iters, uint32_t* status, int* rnd, int* done,
-                                                         int* ndone) {
+__global__ __launch_bounds__(1024) void k_retire_compact(int maxit_all, const int* __restrict__ maxit,
+                                                         int early_stop, int* alist, int* tmp, int* nact_p,
+                                                         uint32_t* unsat, uint32_t* mism, int32_t* iters,
+                                                         uint32_t* status, int* rnd, int* done, int* ndone) {
   __shared__ int wsum[16];
   __shared__ int base_s;
-  retire_compact_body<1024>(maxit_all, maxit, alist, tmp, nact_p, unsat, mism, iters, status, rnd, done, ndone,
-                            wsum, &base_s);
+  retire_compact_body<1024>(maxit_all, maxit, early_stop, alist, tmp, nact_p, unsat, mism, iters, status, rnd, done,
+                            ndone, wsum, &base_s);
 }
 
 // Syndromes of the active frames and, in the workgroup that finishes last, the
@@ -271,8 +328,8 @@ __global__ __launch_bounds__(256) void k_syndrome_retire(DevCode cd, const uint8
                                                          const uint8_t* __restrict__ fsw, uint8_t* __restrict__ synd,
                                                          uint32_t* unsat, uint32_t* mism, int* alist, int* nact_p,
                                                          int* rnd, int maxit_all, const int* __restrict__ maxit,
-                                                         int* tmp, int32_t* iters, uint32_t* status, int* done,
-                                                         int* ndone, unsigned* ticket) {
+                                                         int early_stop, int* tmp, int32_t* iters,
+                                                         uint32_t* status, int* done, int* ndone, unsigned* ticket) {
   extern __shared__ uint32_t smw[];
   __shared__ uint8_t s_exp[512];
   __shared__ uint16_t s_log[256];
@@ -289,8 +346,8 @@ __global__ __launch_bounds__(256) void k_syndrome_retire(DevCode cd, const uint8
   __syncthreads();
   if (!last) return;
   __threadfence();
-  retire_compact_body<256>(maxit_all, maxit, alist, tmp, nact_p, unsat, mism, iters, status, rnd, done, ndone, wsum,
-                           &base_s);
+  retire_compact_body<256>(maxit_all, maxit, early_stop, alist, tmp, nact_p, unsat, mism, iters, status, rnd, done,
+                           ndone, wsum, &base_s);
   if (threadIdx.x == 0) *ticket = 0u;
 }
 

@@ -50,9 +50,9 @@ struct Impl {
   }
   // Edge-parallel pass (k_fused_split) over at most Fmax active frames: one
   // workgroup of KMAX wavefronts per (frame group, check), grid-stride.
-  // Built forms: FP64 variable node with FP32/FP16 storage, symbol priors
-  // with FP32 storage (the entry points reject the other combinations); the
-  // FP32 forms with every storage type.
+  // Built forms: every variable-node form with FP32 storage; the default
+  // form (kProbPrior) only with 16-bit storage, whose words are message pmfs
+  // (the entry points reject the other combinations).
   template <typename S>
   static void fused_split(const FusedArgs& a, hipStream_t s) {
     const long items = (long)((a.Fmax + G::T - 1) / G::T) * a.cd.M;
@@ -63,23 +63,23 @@ struct Impl {
 #define LFD_SPLIT(AR)                                                                                           \
   hipLaunchKernelGGL((k_fused_split<G, KMAX, S, AR>), grid, block, lds_bytes, s, a.cd, a.prior, b0, b1, a.hard, \
                      a.fsw, a.alist, a.nact, a.rnd, a.maxit, a.maxit_all)
-    if constexpr (!std::is_same_v<S, bf16_t>) {
+    if constexpr (kPmfWords<S>) {
+      LFD_SPLIT(kProbPrior);   // 16-bit storage: the default variable node only
+    } else {
       if (a.ar == kFp64) {
         LFD_SPLIT(kFp64);
         return;
       }
-    }
-    if (a.ar == kProbPrior) {
-      LFD_SPLIT(kProbPrior);
-      return;
-    }
-    if constexpr (std::is_same_v<S, float>) {
+      if (a.ar == kProbPrior) {
+        LFD_SPLIT(kProbPrior);
+        return;
+      }
       if (a.ar == kSymbolPrior) {
         LFD_SPLIT(kSymbolPrior);
         return;
       }
+      LFD_SPLIT(kFp32);
     }
-    LFD_SPLIT(kFp32);
 #undef LFD_SPLIT
   }
   template <typename S>
@@ -90,29 +90,29 @@ struct Impl {
 #define LFD_FUSED(AR, DM)                                                                                          \
   hipLaunchKernelGGL((k_fused<G, KMAX, S, AR, DM>), grid, block, lds(), s, a.cd, a.prior, b0, b1, a.hard, a.fsw, \
                      a.alist, a.nact, a.rnd, a.maxit, a.maxit_all)
-    if constexpr (kMfmaDecision<G>) {
-      if (a.mfma && a.ar == kFp32) {
-        LFD_FUSED(kFp32, true);
-        return;
+    if constexpr (kPmfWords<S>) {
+      LFD_FUSED(kProbPrior, false);   // 16-bit storage: the default variable node only
+    } else {
+      if constexpr (kMfmaDecision<G>) {
+        if (a.mfma && a.ar == kFp32) {
+          LFD_FUSED(kFp32, true);
+          return;
+        }
       }
-    }
-    if constexpr (!std::is_same_v<S, bf16_t>) {
       if (a.ar == kFp64) {
         LFD_FUSED(kFp64, false);
         return;
       }
-    }
-    if (a.ar == kProbPrior) {
-      LFD_FUSED(kProbPrior, false);
-      return;
-    }
-    if constexpr (std::is_same_v<S, float>) {
+      if (a.ar == kProbPrior) {
+        LFD_FUSED(kProbPrior, false);
+        return;
+      }
       if (a.ar == kSymbolPrior) {
         LFD_FUSED(kSymbolPrior, false);
         return;
       }
+      LFD_FUSED(kFp32, false);
     }
-    LFD_FUSED(kFp32, false);
 #undef LFD_FUSED
   }
   static bool fused_pass(const FusedArgs& a, hipStream_t s) {

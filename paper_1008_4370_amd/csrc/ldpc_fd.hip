@@ -33,6 +33,9 @@ int32_t fail(int32_t code, const std::string& msg) {
 
 const uint32_t kDefaultPoly[9] = {0, 0x3, 0x7, 0xB, 0x13, 0x25, 0x43, 0x89, 0x11D};
 
+const char* const kPmfOnlyDefault =
+    "16-bit storage holds message pmfs, which only the default variable node (PRECISE = 2) reads";
+
 }  // namespace
 
 struct ldpc_fd_code_s {
@@ -66,7 +69,7 @@ struct ldpc_fd_code_s {
   // Captured chunks of rounds of the fused decoder, keyed by everything their
   // kernel arguments depend on.
   struct GraphKey {
-    int F, prec, chunk, max_iter, logr, blocks, tail, ar;
+    int F, prec, chunk, max_iter, logr, blocks, tail, ar, early;
     const void *ws, *llr, *hard, *synd, *iters, *status;
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
   };
@@ -235,6 +238,22 @@ void launch_prior(const ldpc_fd_code_s* c, int F, const float* llr, float* prior
                      prior, n, c->precise ? 1 : 0);
 }
 
+// Conversions between the FP32 signed-log message layout and 16-bit pmf
+// words (ldpc_fd_round's import and export), one workgroup per (frame, edge)
+// vector, FP64 transforms.
+template <typename S>
+void launch_lambda_to_pmf(const ldpc_fd_code_s* c, int F, const float* in, S* out, hipStream_t s) {
+  const long nvec = (long)F * c->E;
+  hipLaunchKernelGGL(k_lambda_to_pmf<S>, dim3((unsigned)std::min<long>(nvec, 65536)), dim3(std::max(c->q, 64)),
+                     c->q * sizeof(double), s, in, out, nvec, c->q);
+}
+template <typename S>
+void launch_pmf_to_lambda(const ldpc_fd_code_s* c, int F, const S* in, float* out, hipStream_t s) {
+  const long nvec = (long)F * c->E;
+  hipLaunchKernelGGL(k_pmf_to_lambda<S>, dim3((unsigned)std::min<long>(nvec, 65536)), dim3(std::max(c->q, 64)),
+                     c->q * sizeof(double), s, in, out, nvec, c->q);
+}
+
 // Syndromes of the current decisions for the active frames (alist/nact, or all
 // F frames gated by `active`).
 void launch_syndrome(const ldpc_fd_code_s* c, int F, const uint8_t* hard, const uint8_t* fsw, uint8_t* synd,
@@ -257,16 +276,16 @@ void launch_syndrome(const ldpc_fd_code_s* c, int F, const uint8_t* hard, const 
 void launch_syndrome_retire(const ldpc_fd_code_s* c, int F, const uint8_t* hard, const uint8_t* fsw, uint8_t* synd,
                             uint32_t* unsat, uint32_t* mism, int* alist, int* nact, int* rnd, int maxit_all,
                             const int* maxit, int* tmp, int32_t* iters, uint32_t* status, int* done, int* ndone,
-                            int tail_grid, hipStream_t s) {
+                            int tail_grid, hipStream_t s, int early_stop = 1) {
   const size_t lds = 4 * (size_t)(((c->N + 3) >> 2) + ((c->E + 3) >> 2));
   if (tail_grid > 0 && lds <= 60000) {
     hipLaunchKernelGGL(k_syndrome_retire, dim3((unsigned)std::min(F, tail_grid)), dim3(256), lds, s, c->dev, hard, fsw,
-                       synd, unsat, mism, alist, nact, rnd, maxit_all, maxit, tmp, iters, status, done, ndone,
-                       (unsigned*)(nact + 2));
+                       synd, unsat, mism, alist, nact, rnd, maxit_all, maxit, early_stop, tmp, iters, status, done,
+                       ndone, (unsigned*)(nact + 2));
   } else {
     launch_syndrome(c, F, hard, fsw, synd, nullptr, unsat, mism, alist, nact, nullptr, s, rnd);
-    hipLaunchKernelGGL(k_retire_compact, dim3(1), dim3(1024), 0, s, maxit_all, maxit, alist, tmp, nact, unsat, mism,
-                       iters, status, rnd, done, ndone);
+    hipLaunchKernelGGL(k_retire_compact, dim3(1), dim3(1024), 0, s, maxit_all, maxit, early_stop, alist, tmp, nact,
+                       unsat, mism, iters, status, rnd, done, ndone);
   }
 }
 
@@ -454,10 +473,16 @@ int32_t ldpc_fd_workspace_bytes(ldpc_fd_code c, int32_t frames, int32_t prec, in
 namespace {
 
 // Decode from BPSK LLRs (llr) or from symbol priors (prior, FUSED mode only).
+// flags: LDPC_FD_FLAG_NO_EARLY_STOP and LDPC_FD_FLAG_ASYNC (see ldpc_fd_decode_ex).
 int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* prior, int32_t max_iter, int32_t prec,
                     int32_t mode, uint8_t* hard, uint8_t* synd, int32_t* iters, uint32_t* status, void* workspace,
-                    int64_t workspace_bytes, void* stream) {
+                    int64_t workspace_bytes, void* stream, uint32_t flags = 0) {
   if (!c) return fail(LDPC_FD_E_INVALID, "code is NULL");
+  const int early = (flags & LDPC_FD_FLAG_NO_EARLY_STOP) ? 0 : 1;
+  const bool async = (flags & LDPC_FD_FLAG_ASYNC) != 0;
+  if (async && (mode == LDPC_FD_MODE_LOGSP || mode == LDPC_FD_MODE_FSP || (mode == LDPC_FD_MODE_PLAIN && !c->regular)))
+    return fail(LDPC_FD_E_UNSUPPORTED, "asynchronous decoding: FUSED and regular PLAIN only (the list-based "
+                                       "decoders size each round from the host)");
   if (F < 0 || max_iter < 1) return fail(LDPC_FD_E_INVALID, "frames < 0 or max_iter < 1");
   if (F == 0) return LDPC_FD_OK;
   if (!(llr || prior) || !hard || !synd || !iters || !status || !workspace)
@@ -466,8 +491,8 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   if (mode == LDPC_FD_MODE_FUSED && !c->regular)
     return fail(LDPC_FD_E_UNSUPPORTED, "the FUSED decoder needs column weight 2 (PLAIN and LOGSP take any)");
   if (prior && prec != LDPC_FD_FP32) return fail(LDPC_FD_E_UNSUPPORTED, "symbol priors need FP32 storage");
-  if (!prior && c->precise == 1 && prec == LDPC_FD_BF16 && mode == LDPC_FD_MODE_FUSED)
-    return fail(LDPC_FD_E_UNSUPPORTED, "the FP64 variable node needs FP32 or FP16 storage");
+  if (!prior && c->precise != 2 && prec != LDPC_FD_FP32 && mode == LDPC_FD_MODE_FUSED)
+    return fail(LDPC_FD_E_UNSUPPORTED, kPmfOnlyDefault);
   int64_t need = 0;
   int32_t rc = ldpc_fd_workspace_bytes(c, F, prec, mode, &need);
   if (rc) return rc;
@@ -498,7 +523,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
       hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,
-                         iters, status, w.count, w.alist);
+                         iters, status, w.count, w.alist, early);
       int left = 0;
       if ((rc = read_count(w.count, s, &left))) return rc;
       if (left == 0) break;
@@ -536,7 +561,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
       hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,
-                         iters, status, w.count, w.alist);
+                         iters, status, w.count, w.alist, early);
       int left = 0;
       if ((rc = read_count(w.count, s, &left))) return rc;
       if (left == 0) break;
@@ -563,7 +588,8 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
       hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,
-                         iters, status, w.count, (int*)nullptr);
+                         iters, status, w.count, (int*)nullptr, early);
+      if (async) continue;   // every round is enqueued; the kernels skip stopped frames
       int left = 0;
       if ((rc = read_count(w.count, s, &left))) return rc;
       if (left == 0) break;
@@ -595,7 +621,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     ok = run_fused(c, lr, fa, st);
     if (e1) (void)hipEventRecord(e1, st);
     launch_syndrome_retire(c, F, hard, w.fsw, synd, w.unsat, w.mism, w.alist, w.nact, w.rnd, max_iter, nullptr, w.tmp,
-                           iters, status, nullptr, nullptr, tail ? std::max(c->tail_frames, 1) : 0, st);
+                           iters, status, nullptr, nullptr, tail ? std::max(c->tail_frames, 1) : 0, st, early);
     return ok;
   };
   // A frame needs at most max_iter + 1 passes (pass l forms round l's decision).
@@ -603,7 +629,8 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   // Kernel timing needs per-launch events, which HIP cannot time inside a
   // replayed graph: profiled decodes launch every pass from the host.
   // Kernel variant of a chunk of passes, from the active count at its start.
-  auto is_tail = [&](int left) { return left <= c->tail_frames; };
+  // (asynchronous decodes never learn the active count: full variant throughout)
+  auto is_tail = [&](int left) { return !async && left <= c->tail_frames; };
   auto variant = [&](int left) { return is_tail(left) ? c->tail_logr : c->logr; };
   if (!c->graphs || t_prof.on) {
     int lr = variant(F);
@@ -616,7 +643,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
         if (e0 && e1) t_prof.ev[LDPC_FD_K_FUSED].emplace_back(e0, e1);
       }
       if (!enqueue_round(s, e0, e1, lr, tail)) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
-      if (p % c->chunk == 0 || p == passes) {
+      if (!async && (p % c->chunk == 0 || p == passes)) {
         int left = 0;
         if ((rc = read_count(w.nact, s, &left))) return rc;
         if (left == 0) break;
@@ -644,6 +671,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     key.blocks = c->blocks;
     key.tail = tail ? 1 : 0;
     key.ar = ar;
+    key.early = early;
     key.ws = workspace;
     key.llr = tp;
     key.hard = hard;
@@ -679,6 +707,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     hipGraphExec_t exec = nullptr;
     if ((rc = chunk_graph(variant(left), is_tail(left), &exec))) return rc;
     HIP_TRY(hipGraphLaunch(exec, s));
+    if (async) continue;   // passes after the last frame stops find no active frame
     if ((rc = read_count(w.nact, s, &left))) return rc;
     if (left == 0) break;
   }
@@ -724,8 +753,8 @@ int32_t round_check(ldpc_fd_code c, int32_t F, const float* llr, const float* c2
   if (mode == LDPC_FD_MODE_FUSED && v2c_out) return fail(LDPC_FD_E_INVALID, "FUSED round does not form v2c_out");
   if (mode == LDPC_FD_MODE_FUSED && !c->regular)
     return fail(LDPC_FD_E_UNSUPPORTED, "the FUSED decoder needs column weight 2 (PLAIN and LOGSP take any)");
-  if (mode == LDPC_FD_MODE_FUSED && c->precise == 1 && prec == LDPC_FD_BF16)
-    return fail(LDPC_FD_E_UNSUPPORTED, "the FP64 variable node needs FP32 or FP16 storage");
+  if (mode == LDPC_FD_MODE_FUSED && c->precise != 2 && prec != LDPC_FD_FP32)
+    return fail(LDPC_FD_E_UNSUPPORTED, kPmfOnlyDefault);
   if (mode < LDPC_FD_MODE_PLAIN || mode > LDPC_FD_MODE_FSP) return fail(LDPC_FD_E_INVALID, "unknown mode");
   if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
   if (mode != LDPC_FD_MODE_FUSED && prec != LDPC_FD_FP32)
@@ -811,22 +840,21 @@ int32_t round_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* c2v
   } else {
     // Frames at round 1 read buffer 1 and write buffer 0; frames at round 0
     // (no imported state) write buffer 1.  16-bit storage: the imported state
-    // is rounded to the storage type first and the result widened back.
+    // is converted to the stored word (the pmf times q, rounded) first and
+    // the stored result converted back to normalised signed-log words.
     auto run = [&](auto tag) {
       using S = decltype(tag);
       S* in = (S*)c2v_in;
       S* out = (S*)c2v_out;
-      const unsigned g = (unsigned)std::min<size_t>((n_msg / 4 + 255) / 256, 65536);
-      if (prec != LDPC_FD_FP32) {
+      if constexpr (kPmfWords<S>) {
         in = (S*)t.st_in;
         out = (S*)t.st_out;
-        if (c2v_in) hipLaunchKernelGGL((k_convert<float, S>), dim3(g), dim3(256), 0, s, c2v_in, in, n_msg / 4);
+        if (c2v_in) launch_lambda_to_pmf<S>(c, F, c2v_in, in, s);
       }
       const FusedArgs fa{cd, F, prior, c2v_in ? (void*)out : nullptr, c2v_in ? (void*)in : (void*)out, hard, fsw,
                          alist, nact, rnd, nullptr, 1 << 30, c->blocks, var_form(c->precise), c->mfma != 0, prec, false};
       ok = run_fused(c, c->logr, fa, s);
-      if (prec != LDPC_FD_FP32)
-        hipLaunchKernelGGL((k_convert<S, float>), dim3(g), dim3(256), 0, s, (const S*)out, c2v_out, n_msg / 4);
+      if constexpr (kPmfWords<S>) launch_pmf_to_lambda<S>(c, F, (const S*)out, c2v_out, s);
     };
     if (prec == LDPC_FD_FP32) run(float{});
     else if (prec == LDPC_FD_FP16) run(_Float16{});
@@ -1006,3 +1034,86 @@ int32_t ldpc_fd_profile_read(int32_t kernel, double* ms, int64_t* launches) {
 
 #include "pool.inc"
 #include "posterior.inc"
+
+// ===========================================================================
+// Decode with the argument struct and flags, several rounds from an imported
+// state, and a pool sized from an HBM budget.
+extern "C" {
+
+int32_t ldpc_fd_decode_ex(ldpc_fd_code c, const ldpc_fd_decode_args* a, void* stream) {
+  if (!c || !a) return fail(LDPC_FD_E_INVALID, "NULL code or arguments");
+  const uint32_t known = LDPC_FD_FLAG_NO_EARLY_STOP | LDPC_FD_FLAG_VALIDATION | LDPC_FD_FLAG_ASYNC;
+  if (a->flags & ~known) return fail(LDPC_FD_E_INVALID, "unknown flag bits");
+  if (a->frames > 0 && !a->llr) return fail(LDPC_FD_E_INVALID, "NULL buffer");
+  const bool val = (a->flags & LDPC_FD_FLAG_VALIDATION) != 0;
+  if (val && a->mode != LDPC_FD_MODE_FUSED)
+    return fail(LDPC_FD_E_UNSUPPORTED, "validation posteriors follow a FUSED decode");
+  if (val && a->frames > 0 && !a->posterior) return fail(LDPC_FD_E_INVALID, "VALIDATION needs a posterior buffer");
+  int32_t rc = decode_impl(c, a->frames, a->llr, nullptr, a->max_iter, a->prec, a->mode, a->hard, a->synd, a->iters,
+                           a->status, a->workspace, a->workspace_bytes, stream, a->flags);
+  if (rc || !val || a->frames == 0) return rc;
+  return ldpc_fd_decode_posterior(c, a->frames, a->llr, a->prec, a->iters, a->workspace, a->workspace_bytes,
+                                  a->posterior, stream);
+}
+
+int32_t ldpc_fd_run_rounds(ldpc_fd_code c, int32_t F, const float* llr, int32_t rounds, int32_t from_channel,
+                           float* c2v_inout, uint8_t* hard, uint8_t* fsynd, uint8_t* synd, int32_t mode, int32_t prec,
+                           void* stream) {
+  if (!c) return fail(LDPC_FD_E_INVALID, "code is NULL");
+  if (rounds < 1 || rounds > 100000) return fail(LDPC_FD_E_INVALID, "rounds outside 1..100000");
+  if (!c2v_inout && F > 0) return fail(LDPC_FD_E_INVALID, "NULL c2v_inout");
+  const bool decides = !from_channel || rounds > 1;
+  int32_t rc = round_check(c, F, llr, decides ? c2v_inout : nullptr, mode == LDPC_FD_MODE_FUSED ? nullptr : c2v_inout,
+                           c2v_inout, hard, fsynd, synd, mode, prec);
+  if (rc || F == 0) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t msg = align256((size_t)F * c->E * c->q * 4);
+  const size_t tmp_bytes = round_layout(c, F, prec, nullptr, nullptr);
+  char* mem = nullptr;
+  HIP_TRY(hipMalloc((void**)&mem, 2 * msg + tmp_bytes));
+  float* other = (float*)mem;                 // the state of the alternate rounds
+  float* v2c = (float*)(mem + msg);           // variable-to-check messages (PLAIN, LOGSP, FSP)
+  char* tmp = mem + 2 * msg;
+  float* cur = c2v_inout;
+  float* nxt = other;
+  for (int r = 0; r < rounds && rc == LDPC_FD_OK; ++r) {
+    const float* in = (r == 0 && from_channel) ? nullptr : cur;
+    rc = round_impl(c, F, llr, in, mode == LDPC_FD_MODE_FUSED ? nullptr : v2c, nxt, hard, fsynd, synd, mode, prec, s,
+                    tmp);
+    std::swap(cur, nxt);
+  }
+  // the last round's output is in `cur`
+  if (rc == LDPC_FD_OK && cur != c2v_inout)
+    rc = hipMemcpyAsync(c2v_inout, cur, (size_t)F * c->E * c->q * 4, hipMemcpyDeviceToDevice, s) == hipSuccess
+             ? LDPC_FD_OK
+             : fail(LDPC_FD_E_HIP, "hipMemcpyAsync");
+  hipError_t e1 = hipStreamSynchronize(s);
+  hipError_t e2 = hipFree(mem);
+  if (rc) return rc;
+  if (e1 != hipSuccess) return fail(LDPC_FD_E_HIP, std::string("run_rounds: ") + hipGetErrorString(e1));
+  if (e2 != hipSuccess) return fail(LDPC_FD_E_HIP, std::string("hipFree: ") + hipGetErrorString(e2));
+  return LDPC_FD_OK;
+}
+
+int32_t ldpc_fd_pool_create_budget(const ldpc_fd_code* codes, int32_t ncodes, int64_t hbm_budget, int32_t prec,
+                                   void* stream, ldpc_fd_pool* out) {
+  if (!out) return fail(LDPC_FD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!codes || ncodes < 1 || ncodes > 16) return fail(LDPC_FD_E_INVALID, "1..16 codes required");
+  if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
+  if (hbm_budget < 1) return fail(LDPC_FD_E_INVALID, "budget must be positive");
+  std::vector<int32_t> slots(ncodes);
+  const int64_t share = hbm_budget / ncodes;
+  for (int k = 0; k < ncodes; ++k) {
+    if (!codes[k]) return fail(LDPC_FD_E_INVALID, "NULL code");
+    const int64_t per = (int64_t)pool_slot_bytes(codes[k], prec);
+    const int64_t n = share / per;
+    if (n < 1)
+      return fail(LDPC_FD_E_NOMEM, "the budget's share of code " + std::to_string(k) + " holds no frame slot (" +
+                                       std::to_string(per) + " bytes each)");
+    slots[k] = (int32_t)std::min<int64_t>(n, 1 << 22);
+  }
+  return ldpc_fd_pool_create(codes, ncodes, slots.data(), prec, stream, out);
+}
+
+}  // extern "C"

@@ -357,12 +357,18 @@ struct IO<float> {
     *reinterpret_cast<float4*>(p) = make_float4(i[0], i[1], i[2], i[3]);
   }
 };
-// FP16 words hold 512 * (-log2|P|): magnitudes up to 100 * 512 = 51200 stay
-// below the FP16 maximum, and the 11-bit relative precision reaches down to
-// -log2|P| = 2^-23 before subnormals.  Messages close to certainty (|P| = 1 -
-// delta, magnitude ~ delta / ln 2) carry the small symbol probabilities in
-// delta, which an unscaled FP16 word would flush into its subnormal range.
-constexpr float kHalfScale = 512.0f;
+// 16-bit storage holds a different word than FP32: not the signed-log
+// Fourier value but the message's pmf scaled by q, q p(x) = sum_z P(z)
+// (-1)^(x.z) (the inverse transform of P, clamped at zero; in [0, q] since
+// P(0) = 1).  A 16-bit float then keeps every probability to a relative
+// precision of 2^-11 (FP16) or 2^-8 (BF16), whereas a 16-bit signed-log
+// Fourier word carries P(z) to an absolute ~1e-4, which swamps the small
+// probabilities that decide near-certain messages.  The variable node needs
+// the pmf anyway (it multiplies the message pmf with the channel pmf), so the
+// transform moves from each load to the store of the check node's output.
+// FP16 values below 2^-14 are subnormal (q p(x) down to 2^-24 is kept).
+template <typename S>
+constexpr bool kPmfWords = !__is_same(S, float);
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 template <>
 struct IO<_Float16> {
@@ -373,17 +379,17 @@ struct IO<_Float16> {
   }
   static __device__ __forceinline__ float entry(const uint32_t* w, int i) {
     const uint16_t b = (uint16_t)((i & 1) ? (w[i >> 1] >> 16) : (w[i >> 1] & 0xFFFFu));
-    return (float)__builtin_bit_cast(_Float16, b) * (1.0f / kHalfScale);
+    return (float)__builtin_bit_cast(_Float16, b);
   }
   static __device__ __forceinline__ void load4(const _Float16* p, float* o) {
     const half4_t x = *reinterpret_cast<const half4_t*>(p);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = (float)x[i] * (1.0f / kHalfScale);
+    for (int i = 0; i < 4; ++i) o[i] = (float)x[i];
   }
   static __device__ __forceinline__ void store4(_Float16* p, const float* i) {
     half4_t x;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) x[k] = (_Float16)(i[k] * kHalfScale);
+    for (int k = 0; k < 4; ++k) x[k] = (_Float16)i[k];
     *reinterpret_cast<half4_t*>(p) = x;
   }
 };

@@ -109,6 +109,19 @@ __device__ __forceinline__ void decide_pmf(const float (&pp)[G::R], float (&Xo)[
   decide_signs<G>(Xo, lds, rb, cf, zl, cols_a, cols_b, hard, fa, fb);
 }
 
+// The same decision when the own message arrives as its pmf (16-bit storage,
+// kPmfWords): the posterior pmf is pp . xo directly, one transform gives Q.
+// xo is overwritten.
+template <class G>
+__device__ __forceinline__ void decide_pmf_direct(const float (&pp)[G::R], float (&xo)[G::R], float* lds, int rb,
+                                                  int cf, int zl, uint64_t cols_a, uint64_t cols_b, int& hard,
+                                                  int& fa, int& fb) {
+#pragma unroll
+  for (int r = 0; r < G::R; ++r) xo[r] *= pp[r];
+  wht_s<G>(xo, zl);
+  decide_signs<G>(xo, lds, rb, cf, zl, cols_a, cols_b, hard, fa, fb);
+}
+
 // ---- tentative decision on the matrix cores ------------------------------------
 // For the geometry with 4 lanes per frame (16 frames per wavefront, q = 16, 32,
 // 64) the three Hadamard transforms of the decision run as FP16 MFMAs with
@@ -485,6 +498,12 @@ __device__ __forceinline__ void conv_symbol_prior(float (&v)[G::R], const float 
 // from the signed complements u_i = sign(L_i) (1 - |tanh(L_i / 2)|): the less
 // likely value of bit i has probability |u_i| / 2 = 1 / (1 + e^|L_i|), kept at
 // full relative precision, the likelier one 1 - |u_i| / 2.
+// Every entry is the product of its m bit factors taken in bit order 0..m-1,
+// for every lane geometry, so that every layout gives the same FP32 result.
+// The products are formed as a prefix tree in that order: after bit i the
+// lane holds one partial product per pattern of the register bits among
+// 0..i (the lane bits are fixed per lane), so a lane with R entries spends
+// sum_i 2^(register bits <= i) multiplies instead of R (m - 1).
 template <class G>
 __device__ __forceinline__ void prob_prior(const float (&u)[G::LOGQ], int zl, float (&pr)[G::R]) {
   float p0[G::LOGQ], p1[G::LOGQ];
@@ -495,15 +514,55 @@ __device__ __forceinline__ void prob_prior(const float (&u)[G::LOGQ], int zl, fl
     p0[i] = zero_likelier ? 1.0f - a : a;
     p1[i] = zero_likelier ? a : 1.0f - a;
   }
-  // factors multiplied in bit order 0..m-1 for every geometry, so that every
-  // lane layout gives the same FP32 result
+  // pr[k] for k < 2^n holds the product over bits 0..i for the register-bit
+  // pattern k (register bits numbered in bit order, which is the order of
+  // the register index r: see Geo::reg_bit)
+  pr[0] = 1.0f;
+  int n = 0;
 #pragma unroll
-  for (int r = 0; r < G::R; ++r) {
-    const int z = G::z_of(zl, r);
-    float v = 1.0f;
+  for (int i = 0; i < G::LOGQ; ++i) {
+    if (G::lane_bit(i)) {
+      const float f = ((zl >> G::lane_shift(i)) & 1) ? p1[i] : p0[i];
 #pragma unroll
-    for (int i = 0; i < G::LOGQ; ++i) v *= ((z >> i) & 1) ? p1[i] : p0[i];
-    pr[r] = v;
+      for (int k = 0; k < G::R; ++k)
+        if (k < (1 << n)) pr[k] *= f;
+    } else {
+#pragma unroll
+      for (int k = G::R - 1; k >= 0; --k)
+        if (k < (1 << n)) {
+          pr[k | (1 << n)] = pr[k] * p1[i];
+          pr[k] *= p0[i];
+        }
+      ++n;
+    }
+  }
+}
+
+// The check node's output for edge j in check coordinates, total minus own:
+// the signed-log word Lambda~_cv (FP32 storage), or, for 16-bit storage
+// (kPmfWords), already the linear value Gamma^-1(Lambda~_cv) = sign 2^-mag
+// (the map is entrywise, so it may precede the inverse label permutation).
+template <typename S, typename Acc>
+__device__ __forceinline__ float check_output(Acc smag, uint32_t ssgn, float own) {
+  const float mag = __builtin_amdgcn_fmed3f((float)(smag - (Acc)__builtin_fabsf(own)), 0.0f, kLmax);
+  const uint32_t sgn = (ssgn ^ __float_as_uint(own)) & 0x80000000u;
+  if constexpr (kPmfWords<S>)
+    return __uint_as_float(sgn | __float_as_uint(__builtin_amdgcn_exp2f(-mag)));
+  else
+    return __uint_as_float(sgn | __float_as_uint(mag));
+}
+
+// The check node's output (variable coordinates, as check_output forms it) in
+// the storage's word format: unchanged for FP32 storage; for 16-bit storage
+// the message pmf times q, the transform of P with its negative rounding
+// residue set to zero.
+template <class G, typename S>
+__device__ __forceinline__ void to_storage_word(float (&o)[G::R], int zl) {
+  if constexpr (kPmfWords<S>) {
+    const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
+    wht_s<G>(o, zl);
+#pragma unroll
+    for (int r = 0; r < G::R; ++r) o[r] = __builtin_fmaxf(o[r] * sz, 0.0f);
   }
 }
 
@@ -515,12 +574,16 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
                                            S* __restrict__ buf1, uint8_t* __restrict__ hard,
                                            uint8_t* __restrict__ fsw, int f, bool valid, const FrameState& fs,
                                            int c, float* lds, int rb, int cf, int zl) {
+  static_assert(!kPmfWords<S> || AR == kProbPrior, "16-bit storage (pmf words) takes the default variable node");
   const int e0 = uni(cd.row_ptr[c]), deg = uni(cd.row_ptr[c + 1]) - e0;
   const size_t fb = (size_t)f * cd.E * G::Q;
   const S* cin = (fs.ell & 1) ? buf1 : buf0;
   S* cout = (fs.ell & 1) ? buf0 : buf1;
   const bool any_decide = __builtin_amdgcn_ballot_w64(fs.decide && valid) != 0;
   const bool any_write = __builtin_amdgcn_ballot_w64(fs.write && valid) != 0;
+  // some frame of the wave at round 0 (no incoming state): only then the
+  // per-entry choice between the initial and the loaded message is needed
+  const bool any_first = __builtin_amdgcn_ballot_w64(fs.first) != 0;
   float st[KMAX][G::R];   // Lambda~_vc of each edge (check coordinates)
   // sum of magnitudes over the check's edges (P: FP64, so that a small
   // extrinsic sum next to a large own term survives total minus own)
@@ -563,6 +626,32 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
         conv_prior_d<G>(y64, t);
 #pragma unroll
         for (int r = 0; r < G::R; ++r) st[j][r] = (float)y64[r];
+      } else if constexpr (kPmfWords<S>) {
+        // the stored word is the other message's pmf (times q): the product
+        // with the channel pmf needs no transform
+        float pr[G::R];
+        prob_prior<G>(t, zl, pr);
+        if (any_first) {
+#pragma unroll
+          for (int r = 0; r < G::R; ++r) st[j][r] = fs.first ? pr[r] : pr[r] * cur.x(r);
+        } else {
+#pragma unroll
+          for (int r = 0; r < G::R; ++r) st[j][r] = pr[r] * cur.x(r);
+        }
+        if (any_decide && e < eo) {
+          float xo[G::R];
+#pragma unroll
+          for (int r = 0; r < G::R; ++r) xo[r] = cur.o(r);
+          int hd, fa, fo;
+          const int ho = uni(cd.e_label[eo]);
+          decide_pmf_direct<G>(st[j], xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
+          if (valid && fs.decide && zl == 0) {
+            hard[(size_t)f * cd.N + v] = (uint8_t)hd;
+            fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
+            fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
+          }
+        }
+        symbol_prior_back<G>(st[j], zl);
       } else {
 #pragma unroll
         for (int r = 0; r < G::R; ++r)
@@ -636,11 +725,9 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
       const int hinv = uni(cd.ginv[cd.e_label[e]]);
       float o[G::R];
 #pragma unroll
-      for (int r = 0; r < G::R; ++r) {
-        const float mag = __builtin_amdgcn_fmed3f((float)(smag[r] - (Acc)__builtin_fabsf(st[j][r])), 0.0f, kLmax);
-        o[r] = __uint_as_float(((ssgn[r] ^ __float_as_uint(st[j][r])) & 0x80000000u) | __float_as_uint(mag));
-      }
+      for (int r = 0; r < G::R; ++r) o[r] = check_output<S, Acc>(smag[r], ssgn[r], st[j][r]);
       permute<G>(o, lds, rb, cf, zl, uni64(cd.colsT[hinv]));
+      to_storage_word<G, S>(o, zl);
       if (valid && fs.write) store_msg<G, S>(cout + fb + (size_t)e * G::Q, zl, o);
     }
   }
@@ -707,6 +794,7 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
   const long items = (long)groups * cd.M;
   const int fl = lane / G::L, zl = lane % G::L;
   const int rb = (j * G::T + fl) * G::QP, cf = G::swz(fl);
+  static_assert(!kPmfWords<S> || AR == kProbPrior, "16-bit storage (pmf words) takes the default variable node");
   constexpr bool P = AR == kFp64;
   using Acc = typename std::conditional<P, double, float>::type;
   for (long it = blockIdx.x; it < items; it += gridDim.x) {
@@ -739,6 +827,25 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
         conv_prior_d<G>(y64, t);
 #pragma unroll
         for (int r = 0; r < G::R; ++r) st[r] = (float)y64[r];
+      } else if constexpr (kPmfWords<S>) {
+        float pr[G::R];
+        prob_prior<G>(t, zl, pr);
+#pragma unroll
+        for (int r = 0; r < G::R; ++r) st[r] = fs.first ? pr[r] : pr[r] * cur.x(r);
+        if (any_decide && e < eo) {
+          float xo[G::R];
+#pragma unroll
+          for (int r = 0; r < G::R; ++r) xo[r] = cur.o(r);
+          int hd, fa, fo;
+          const int ho = uni(cd.e_label[eo]);
+          decide_pmf_direct<G>(st, xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
+          if (valid && fs.decide && zl == 0) {
+            hard[(size_t)f * cd.N + v] = (uint8_t)hd;
+            fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
+            fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
+          }
+        }
+        symbol_prior_back<G>(st, zl);
       } else {
 #pragma unroll
         for (int r = 0; r < G::R; ++r) st[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x(r));
@@ -813,11 +920,9 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
       const int hinv = uni(cd.ginv[cd.e_label[e]]);
       float o[G::R];
 #pragma unroll
-      for (int r = 0; r < G::R; ++r) {
-        const float mag = __builtin_amdgcn_fmed3f((float)(smag[r] - (Acc)__builtin_fabsf(st[r])), 0.0f, kLmax);
-        o[r] = __uint_as_float(((ssgn[r] ^ __float_as_uint(st[r])) & 0x80000000u) | __float_as_uint(mag));
-      }
+      for (int r = 0; r < G::R; ++r) o[r] = check_output<S, Acc>(smag[r], ssgn[r], st[r]);
       permute<G>(o, lds, rb, cf, zl, uni64(cd.colsT[hinv]));
+      to_storage_word<G, S>(o, zl);
       if (valid && fs.write) store_msg<G, S>(cout + fb + (size_t)e * G::Q, zl, o);
     }
     __syncthreads();  // the stash is rewritten by the next item

@@ -60,7 +60,22 @@ _SIGS = {
     "ldpc_fd_pool_harvest": (_i32, [_c_void_p, _i32, _i32, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
                                     ctypes.POINTER(_i32)]),
     "ldpc_fd_pool_active": (_i32, [_c_void_p, _i32, ctypes.POINTER(_i32)]),
+    "ldpc_fd_pool_create_budget": (_i32, [ctypes.POINTER(_c_void_p), _i32, _i64, _i32, _c_void_p,
+                                          ctypes.POINTER(_c_void_p)]),
+    "ldpc_fd_decode_ex": (_i32, [_c_void_p, _c_void_p, _c_void_p]),
+    "ldpc_fd_run_rounds": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _i32, _c_void_p, _c_void_p, _c_void_p,
+                                  _c_void_p, _i32, _i32, _c_void_p]),
 }
+
+FLAG_NO_EARLY_STOP, FLAG_VALIDATION, FLAG_ASYNC = 1, 2, 4
+
+
+class DecodeArgs(ctypes.Structure):
+    """ldpc_fd_decode_args (include/ldpc_fd.h)."""
+    _fields_ = [("frames", _i32), ("max_iter", _i32), ("prec", _i32), ("mode", _i32), ("flags", _u32),
+                ("llr", _c_void_p), ("hard", _c_void_p), ("synd", _c_void_p), ("iters", _c_void_p),
+                ("status", _c_void_p), ("posterior", _c_void_p), ("workspace", _c_void_p),
+                ("workspace_bytes", _i64)]
 
 
 class LdpcFdError(RuntimeError):
@@ -182,6 +197,26 @@ class Decoder:
         self._last = (llr, F)
         return dict(hard=self.hard[:F], synd=self.synd[:F], iters=self.iters[:F], status=self.status[:F])
 
+    def decode_ex(self, llr, max_iter: int, flags: int = 0):
+        """ldpc_fd_decode_ex with `flags` (FLAG_*); with FLAG_VALIDATION the
+        result also holds the FP64 posteriors [F, N, q]."""
+        import torch
+        F = llr.shape[0]
+        assert F <= self.frames and llr.is_contiguous() and llr.dtype == torch.float32
+        assert tuple(llr.shape[1:]) == (self.code.N, self.code.m)
+        post = None
+        if flags & FLAG_VALIDATION:
+            post = torch.empty((F, self.code.N, self.code.q), dtype=torch.float64, device=llr.device)
+        a = DecodeArgs(F, int(max_iter), PREC[self.prec], MODE[self.mode], int(flags), llr.data_ptr(),
+                       self.hard.data_ptr(), self.synd.data_ptr(), self.iters.data_ptr(), self.status.data_ptr(),
+                       None if post is None else post.data_ptr(), self.workspace.data_ptr(), self.ws_bytes)
+        _check(lib().ldpc_fd_decode_ex(self.code.handle, ctypes.byref(a), _stream()))
+        self._last = (llr, F)
+        out = dict(hard=self.hard[:F], synd=self.synd[:F], iters=self.iters[:F], status=self.status[:F])
+        if post is not None:
+            out["posterior"] = post
+        return out
+
     def decode_prior(self, prior, max_iter: int):
         """prior: device float32 [F, N, q] symbol priors (ldpc_fd_decode_prior;
         FUSED mode).  Returns views of the outputs."""
@@ -245,6 +280,22 @@ def round_step(code: Code, llr, c2v_in=None, mode: str = "plain", prec: str = "f
     return dict(c2v=c2v_out, v2c=v2c_out, hard=hard, fsynd=fsynd, synd=synd)
 
 
+def run_rounds(code: Code, llr, rounds: int, c2v=None, mode: str = "fused", prec: str = "fp32"):
+    """ldpc_fd_run_rounds: `rounds` rounds from the FP32 state c2v [F, E, q]
+    (None: from the channel).  Returns the new state and the last decision."""
+    import torch
+    F = llr.shape[0]
+    dev = llr.device
+    state = (torch.empty((F, code.E, code.q), dtype=torch.float32, device=dev) if c2v is None
+             else c2v.clone().contiguous())
+    hard = torch.zeros((F, code.N), dtype=torch.uint8, device=dev)
+    fsynd = torch.zeros((F, code.M), dtype=torch.uint8, device=dev)
+    synd = torch.zeros((F, code.M), dtype=torch.uint8, device=dev)
+    _check(lib().ldpc_fd_run_rounds(code.handle, F, _ptr(llr), int(rounds), 1 if c2v is None else 0, _ptr(state),
+                                    _ptr(hard), _ptr(fsynd), _ptr(synd), MODE[mode], PREC[prec], _stream()))
+    return dict(c2v=state, hard=hard, fsynd=fsynd, synd=synd)
+
+
 def round_step_noalloc(code: Code, llr, c2v_in=None, mode: str = "plain", prec: str = "fp32"):
     """ldpc_fd_round_noalloc: the same round with the library's static scratch
     (no device allocation inside the call, no synchronisation)."""
@@ -292,14 +343,28 @@ def pool_slot_bytes(code: Code, prec: str = "fp32") -> int:
 class Pool:
     """Continuous-batching decode pool over several codes (ldpc_fd_pool_*)."""
 
-    def __init__(self, codes, slots, prec: str = "fp32"):
+    def __init__(self, codes, slots=None, prec: str = "fp32", hbm_budget: int | None = None):
+        """slots: frame slots per code, or None with hbm_budget (bytes) to let
+        the library size them (ldpc_fd_pool_create_budget)."""
         self.codes = list(codes)
-        self.slots = [int(s) for s in slots]
         arr = (ctypes.c_void_p * len(self.codes))(*[c.handle for c in self.codes])
-        sl = (_i32 * len(self.slots))(*self.slots)
         h = ctypes.c_void_p()
-        _check(lib().ldpc_fd_pool_create(arr, len(self.codes), sl, PREC[prec], _stream(), ctypes.byref(h)))
+        if slots is None:
+            if hbm_budget is None:
+                raise ValueError("give slots or hbm_budget")
+            _check(lib().ldpc_fd_pool_create_budget(arr, len(self.codes), int(hbm_budget), PREC[prec], _stream(),
+                                                    ctypes.byref(h)))
+        else:
+            sl = (_i32 * len(slots))(*[int(s) for s in slots])
+            _check(lib().ldpc_fd_pool_create(arr, len(self.codes), sl, PREC[prec], _stream(), ctypes.byref(h)))
         self.handle = h
+        if slots is None:
+            slots = []
+            for k in range(len(self.codes)):
+                n = _i32()
+                _check(lib().ldpc_fd_pool_free_slots(self.handle, k, ctypes.byref(n)))
+                slots.append(n.value)
+        self.slots = [int(s) for s in slots]
         self.prec = prec
         self._bufs = [None] * len(self.codes)
 

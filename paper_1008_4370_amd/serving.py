@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import collections
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -35,20 +35,6 @@ class CodeBank:
     ebn0: np.ndarray        # [P]
     cw: np.ndarray          # [P, B, N] transmitted codewords (host, for FER)
     llr: object             # torch [P, B, N, m] on the device
-
-
-@dataclass
-class Request:
-    rid: int
-    code: int
-    point: int
-    first: int              # first frame in the bank bucket
-    n: int
-    t_arrival: float
-    admitted: int = 0
-    done: int = 0
-    t_done: float = 0.0
-    frame_done: list = field(default_factory=list)
 
 
 def make_banks(specs, snr_range=(2.0, 3.5), snr_points=16, frames_per_point=256, seed=2024, device="cuda"):
@@ -89,18 +75,27 @@ def serve(banks, offered_fps: float, duration_s: float, prec: str = "fp16", max_
           warmup_s: float = 0.5, record: bool = False):
     """Run the serving loop for `duration_s` seconds of arrivals (after a warm-up).
 
+    Requests live in arrays indexed by request id; a harvest's frames are
+    booked with array operations (no per-frame Python work between steps).
     With `record`, the result also lists (code, Eb/N0 index, bank frame,
     iterations, hard decision) for every returned frame."""
     rng = np.random.default_rng(seed)
-    slots = slots_for_budget(banks, hbm_budget, prec)
-    pool = D.Pool([b.gcode for b in banks], slots, prec=prec)
+    pool = D.Pool([b.gcode for b in banks], None, prec=prec, hbm_budget=hbm_budget)
+    slots = pool.slots
     ncodes = len(banks)
     B = banks[0].llr.shape[1]
     req_rate = offered_fps / request_frames
+    cap = int(req_rate * (warmup_s + duration_s) * 1.5) + 1024
+    r_code = np.zeros(cap, np.int64)
+    r_point = np.zeros(cap, np.int64)
+    r_first = np.zeros(cap, np.int64)
+    r_arr = np.zeros(cap, np.float64)
+    r_admitted = np.zeros(cap, np.int64)
+    r_done = np.zeros(cap, np.int64)
+    r_tdone = np.full(cap, np.nan)
     queues = [collections.deque() for _ in range(ncodes)]
-    reqs = {}
     tag_base = 1 << 20                # tag = rid * tag_base + frame index
-    frame_lat, req_lat = [], []
+    lat_arr, lat_val = [], []         # per harvest: arrival times and latencies (arrays)
     info_bits = 0
     frame_err = [0] * ncodes
     frames_done = [0] * ncodes
@@ -108,31 +103,33 @@ def serve(banks, offered_fps: float, duration_s: float, prec: str = "fp16", max_
     t0 = time.perf_counter()
     next_arr = t0 + warmup_s + rng.exponential(1.0 / req_rate)
     t_end = t0 + warmup_s + duration_s
-    rid = 0
+    nreq = 0
+    open_reqs = 0
     measure_start = t0 + warmup_s
     steps = 0
+    bits_per_frame = [b.enc.K * b.code.m for b in banks]
     while True:
         now = time.perf_counter()
         while next_arr <= now and next_arr < t_end:
+            if nreq == cap:
+                raise RuntimeError("request table full")
             k = int(rng.integers(ncodes))
-            p = int(rng.integers(len(banks[k].ebn0)))
-            first = int(rng.integers(0, B - request_frames + 1))
-            r = Request(rid, k, p, first, request_frames, next_arr)
-            reqs[rid] = r
-            queues[k].append(r)
-            rid += 1
+            r_code[nreq], r_point[nreq] = k, int(rng.integers(len(banks[k].ebn0)))
+            r_first[nreq], r_arr[nreq] = int(rng.integers(0, B - request_frames + 1)), next_arr
+            queues[k].append(nreq)
+            nreq += 1
+            open_reqs += 1
             next_arr += rng.exponential(1.0 / req_rate)
         # admission (FIFO per code, partial admission allowed)
         for k in range(ncodes):
             while queues[k]:
-                r = queues[k][0]
-                bank = banks[k]
-                lo = r.first + r.admitted
-                cnt = r.n - r.admitted
-                tags = r.rid * tag_base + np.arange(r.admitted, r.n)
-                got = pool.submit(k, bank.llr[r.point, lo:lo + cnt], tags, max_iter)
-                r.admitted += got
-                if r.admitted < r.n:
+                rid = queues[k][0]
+                lo = int(r_first[rid] + r_admitted[rid])
+                cnt = request_frames - int(r_admitted[rid])
+                tags = rid * tag_base + np.arange(r_admitted[rid], request_frames)
+                got = pool.submit(k, banks[k].llr[r_point[rid], lo:lo + cnt], tags, max_iter)
+                r_admitted[rid] += got
+                if r_admitted[rid] < request_frames:
                     break
                 queues[k].popleft()
         pool.step(passes_per_step)
@@ -140,33 +137,37 @@ def serve(banks, offered_fps: float, duration_s: float, prec: str = "fp16", max_
         now = time.perf_counter()
         for k in range(ncodes):
             tags, it, st, hd = pool.harvest(k, slots[k])
-            if len(tags) == 0:
+            n = len(tags)
+            if n == 0:
                 continue
             t_h = time.perf_counter()
-            for i, t in enumerate(tags):
-                r = reqs[int(t) // tag_base]
-                fi = int(t) % tag_base
-                r.done += 1
-                frame_lat.append((r.t_arrival, t_h - r.t_arrival))
-                frames_done[k] += 1
-                if record:
-                    records.append((k, r.point, r.first + fi, int(it[i]), hd[i].copy()))
-                if not np.array_equal(hd[i], banks[k].cw[r.point, r.first + fi]):
-                    frame_err[k] += 1
-                if r.t_arrival >= measure_start:
-                    info_bits += banks[k].enc.K * banks[k].code.m
-                if r.done == r.n:
-                    r.t_done = t_h
-                    req_lat.append((r.t_arrival, t_h - r.t_arrival))
-                    del reqs[r.rid]
-        if now >= t_end and not reqs:
+            rids = (tags // tag_base).astype(np.int64)
+            fis = (tags % tag_base).astype(np.int64)
+            arr = r_arr[rids]
+            lat_arr.append(arr)
+            lat_val.append(t_h - arr)
+            frames_done[k] += n
+            sent = banks[k].cw[r_point[rids], r_first[rids] + fis]
+            frame_err[k] += int(np.any(hd != sent, axis=1).sum())
+            info_bits += int((arr >= measure_start).sum()) * bits_per_frame[k]
+            if record:
+                records.extend((k, int(r_point[r]), int(r_first[r] + f), int(i), h.copy())
+                               for r, f, i, h in zip(rids, fis, it, hd))
+            np.add.at(r_done, rids, 1)
+            fin = np.unique(rids[r_done[rids] == request_frames])
+            r_tdone[fin] = t_h
+            open_reqs -= len(fin)
+        if now >= t_end and open_reqs == 0:
             break
         if now >= t_end + 30.0:
             raise RuntimeError("serving loop did not drain within 30 s after the last arrival")
     t_last = time.perf_counter()
     pool.close()
-    fl = np.array([l for a, l in frame_lat if a >= measure_start]) * 1e3
-    rl = np.array([l for a, l in req_lat if a >= measure_start]) * 1e3
+    la = np.concatenate(lat_arr) if lat_arr else np.zeros(0)
+    lv = np.concatenate(lat_val) if lat_val else np.zeros(0)
+    fl = lv[la >= measure_start] * 1e3
+    meas = (r_arr[:nreq] >= measure_start) & np.isfinite(r_tdone[:nreq])
+    rl = (r_tdone[:nreq] - r_arr[:nreq])[meas] * 1e3
     elapsed = t_last - measure_start
     out = {
         "offered_fps": offered_fps,
@@ -187,13 +188,17 @@ def serve(banks, offered_fps: float, duration_s: float, prec: str = "fp16", max_
     return out
 
 
-def decode_mixed(pool: D.Pool, llrs, max_iter: int = 100, passes_per_step: int = 4):
+def decode_mixed(pool: D.Pool, llrs, max_iter: int = 100, passes_per_step: int | None = None):
     """Decode one batch per pool code together: every frame is admitted at
-    once (the pool needs as many slots as frames), each step replays one graph
-    that runs `passes_per_step` passes of every code on concurrent streams,
-    and each code is harvested as soon as none of its frames is active (which
-    leaves it out of later steps).  Returns, per code, dict(iters, status,
-    hard) in frame order."""
+    once (the pool needs as many slots as frames).  Default: one pool step of
+    max_iter + 1 passes, i.e. one graph launch that runs every pass of every
+    code on concurrent streams with no host read in between (a frame needs at
+    most max_iter + 1 passes; the passes after a code's frames have all
+    stopped find no active frame), then every code is harvested.  With
+    passes_per_step, steps of that many passes alternate with host reads of
+    the active counts, and a code is harvested (and left out of later steps)
+    as soon as none of its frames is active.  Returns, per code, dict(iters,
+    status, hard) in frame order."""
     ncodes = len(llrs)
     for k, llr in enumerate(llrs):
         F = int(llr.shape[0])
@@ -210,6 +215,11 @@ def decode_mixed(pool: D.Pool, llrs, max_iter: int = 100, passes_per_step: int =
         order = np.argsort(tags)
         got[k] = {"iters": it[order], "status": st[order], "hard": hd[order]}
 
+    if passes_per_step is None:
+        pool.step(max_iter + 1)
+        for k in range(ncodes):
+            harvest(k)
+        return got
     # a code whose frames have all stopped is harvested at once, which takes it
     # out of the following steps
     for _ in range((max_iter + passes_per_step) // passes_per_step + 1):

@@ -48,15 +48,16 @@ def fsynd_near_tie(tc, post: np.ndarray) -> np.ndarray:
     return mask
 
 
-def round_storage(w: np.ndarray, prec: str) -> np.ndarray:
-    """Round FP32 state words to the decoder's 16-bit storage and back: FP16 words
-    hold 512 * word (round to nearest even), BF16 words the top 16 bits of the
-    FP32 word (round to nearest even)."""
-    w = np.asarray(w, dtype=np.float32)
-    if prec == "fp32":
-        return w
+def store_pmf(qp: np.ndarray, prec: str) -> np.ndarray:
+    """Messages as 16-bit storage holds them: qp = q times a message's pmf (for
+    instance the inverse transform of its Fourier image), clamped at zero,
+    rounded to FP32 and then to FP16 (nearest even) or BF16 (nearest even on
+    the FP32 word).  Returns the stored values widened to FP64 (still times q)."""
+    v = np.maximum(np.asarray(qp, dtype=np.float64), 0.0).astype(np.float32)
     if prec == "fp16":
-        return (w * np.float32(512)).astype(np.float16).astype(np.float32) / np.float32(512)
-    u = w.view(np.uint32).astype(np.uint64)
-    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32)
+        return v.astype(np.float16).astype(np.float64)
+    if prec == "bf16":
+        u = v.view(np.uint32).astype(np.uint64)
+        r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+        return r.astype(np.uint32).view(np.float32).astype(np.float64)
+    raise ValueError(prec)

@@ -9,9 +9,9 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle.sp import TannerCode, decode as odecode  # noqa: E402
 from paper_1008_4370_amd import autotune, serving, synth  # noqa: E402
 from paper_1008_4370_amd import decoder as D  # noqa: E402
+from tests._oracle_pool import oracle_decode_sample  # noqa: E402
 from tests.test_gpu_parity import _check_outputs, _dev  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -19,36 +19,44 @@ pytestmark = pytest.mark.gpu
 
 def test_gf256_n512_8192_frames_per_storage_type():
     """GF(256) (2,8) N=512 at 3.0 dB, 8192 frames: every storage type gives
-    self-consistent outputs; with FP32 storage a sampled frame equals the
-    oracle's decode (one frame: the oracle's direct q^2 convolutions take tens
-    of seconds per GF(256) frame); the FER of each 16-bit type against FP32 is
-    printed (the FER delta of this configuration)."""
+    self-consistent outputs; on a 32-frame sample decoded by the FP64 oracle
+    (spread over host processes: its direct q^2 convolutions take tens of
+    seconds per GF(256) frame) frames that stop at the oracle's round carry its
+    decision, and at least 30 (FP32, FP16) / 28 (BF16) of the 32 are identical
+    to it; the FER of every storage type is printed beside the oracle
+    sample's (the FER delta of this configuration against FP32 on all 8192
+    frames; against the oracle only on the sample, whose few frames cannot
+    resolve FERs near 1e-3)."""
     b = synth.make_batch("gf256_n512")
     F = b.llr.shape[0]
     print(f"[case] gf256_n512 {F} frames", flush=True)
+    sample = np.linspace(0, F - 1, 32).astype(int)
+    rhard, riters, rconv = oracle_decode_sample(b.code, b.llr[sample], 100)
     gcode = D.Code.from_synth(b.code)
     L = _dev(b.llr)
     fers = {}
-    outs = {}
+    floor = {"fp32": 30, "fp16": 30, "bf16": 28}
     for prec in ("fp32", "fp16", "bf16"):
         autotune.apply(gcode, prec, F)
         r = {k: v.cpu().numpy() for k, v in D.decode(gcode, L, 100, prec=prec).items()}
         _check_outputs(r, b.enc, 100)
         fers[prec] = float(np.any(r["hard"] != b.cw, axis=1).mean())
-        outs[prec] = r
+        hard, iters = r["hard"][sample], r["iters"][sample]
+        same_round = (iters == riters) & rconv
+        ident = (iters == riters) & np.all(hard == rhard, axis=1)
+        print(f"[gf256_n512] {prec}: FER {fers[prec]:.5f} (delta vs fp32 {fers[prec] - fers['fp32']:+.5f}); "
+              f"oracle sample identical {ident.sum()}/32, sample FER GPU "
+              f"{np.mean(np.any(hard != b.cw[sample], axis=1)):.3f} oracle {np.mean(~rconv):.3f}", flush=True)
+        assert np.all(np.all(hard[same_round] == rhard[same_round], axis=1))
+        assert ident.sum() >= floor[prec]
     gcode.close()
-    print(f"[gf256_n512] FER fp32 {fers['fp32']:.5f} fp16 {fers['fp16']:.5f} bf16 {fers['bf16']:.5f}", flush=True)
     assert fers["fp32"] < 0.01
-    idx = np.array([F // 2 + 1])
-    tc = TannerCode(b.code.M, b.code.N, b.code.m, b.code.row_ptr, b.code.col, b.code.val, b.code.poly)
-    ref = odecode(tc, b.llr[idx], 100)
-    assert np.all(np.all(outs["fp32"]["hard"][idx] == ref.hard, axis=1))
-    assert np.array_equal(outs["fp32"]["iters"][idx], ref.iters)
 
 
 def test_uneven_three_code_batch_in_one_pool_equals_each_code_alone():
     """3000 x GF(16) N=2048 + 6000 x GF(64) N=512 + 2000 x GF(256) k=16 N=256 at
-    2.5 dB decoded together in one pool (one graph replay per step runs every
+    2.5 dB decoded together in one pool, as one step of every pass (one graph
+    launch) and as steps of 4 passes (one graph replay per step runs every
     code): per-frame results equal those of each code's batch decoded alone."""
     batches = [synth.make_batch(w) for w in ("gf16_n2048", "gf64_n512", "gf256_n256_k16")]
     print("[case] mixed batch 11000 frames", flush=True)
@@ -57,15 +65,18 @@ def test_uneven_three_code_batch_in_one_pool_equals_each_code_alone():
         autotune.apply(c, "fp32", b.llr.shape[0])
     llrs = [_dev(b.llr) for b in batches]
     pool = D.Pool(codes, [b.llr.shape[0] for b in batches], prec="fp32")
-    mixed = serving.decode_mixed(pool, llrs, 100, 4)
+    # one launch of every pass, and steps of 4 passes with host reads between
+    runs = [serving.decode_mixed(pool, llrs, 100), serving.decode_mixed(pool, llrs, 100, 4)]
     pool.close()
-    for c, b, l, r in zip(codes, batches, llrs, mixed):
+    for i, (c, b, l) in enumerate(zip(codes, batches, llrs)):
         alone = {k: v.cpu().numpy() for k, v in D.decode(c, l, 100).items()}
-        assert np.array_equal(r["hard"], alone["hard"])
-        assert np.array_equal(r["iters"], alone["iters"])
-        conv = (r["status"] & D.STATUS_CONVERGED) != 0
-        assert np.array_equal(conv, (alone["status"] & D.STATUS_CONVERGED) != 0)
-        print(f"[mixed] GF({b.code.q}) N={b.code.N}: FER {np.any(r['hard'] != b.cw, axis=1).mean():.4f}",
+        for mixed in runs:
+            r = mixed[i]
+            assert np.array_equal(r["hard"], alone["hard"])
+            assert np.array_equal(r["iters"], alone["iters"])
+            conv = (r["status"] & D.STATUS_CONVERGED) != 0
+            assert np.array_equal(conv, (alone["status"] & D.STATUS_CONVERGED) != 0)
+        print(f"[mixed] GF({b.code.q}) N={b.code.N}: FER {np.any(runs[0][i]['hard'] != b.cw, axis=1).mean():.4f}",
               flush=True)
     for c in codes:
         c.close()

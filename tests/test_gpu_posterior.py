@@ -6,9 +6,10 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle.sp import channel_prior, decode as odecode, run_rounds, tentative  # noqa: E402
+from oracle.gf import hadamard  # noqa: E402
+from oracle.sp import channel_prior, check_to_var, decode as odecode, run_rounds, tentative, var_to_check  # noqa: E402
 from paper_1008_4370_amd import decoder as D  # noqa: E402
-from tests._msg import TOL_FP32, to_state  # noqa: E402
+from tests._msg import TOL_FP32, fourier, from_state, to_state  # noqa: E402
 from tests.test_gpu_parity import CASES, _dev, _setup  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -51,23 +52,58 @@ def test_posterior_from_state_and_after_one_round(case):
         err = _rel_err(got, ref)
         print(f"  state {i + 1}: posterior rel err {err:.2e}", flush=True)
         assert err < 1e-5
-    # (2) one FP32 GPU round from the oracle's state, then the posterior
+    # (2) one FP32 GPU round from the oracle's state (as FP32 words), then the
+    # posterior.  Reference: the exact round from the same words, their pmfs
+    # clamped at zero as the default variable node does (a rounded word vector
+    # is not quite the transform of a nonnegative pmf).  Conditioning: the
+    # kernel computes with P(z) = sign 2^-|w| and the channel pmf in FP32
+    # (relative rounding), and forms each variable-to-check Fourier image
+    # Y(z) / Y(0), |Y(z) / Y(0)| <= 1, in FP32, i.e. to an absolute 2^-24,
+    # which for near-certain messages is a large relative error on 1 - |Y|.
+    # The reference is recomputed with each P(z) and channel probability moved
+    # by a random relative 2^-22 and each normalised Y(z) by a random
+    # absolute 2^-22 (four units in the last place).  Every symbol whose
+    # posterior moves by less than 1e-5 (relative to its largest probability)
+    # is well-conditioned and held to 1e-4; the others (a small Y(0) where
+    # prior and message disagree, or a posterior made of near-certain
+    # messages' small probabilities) are counted and printed.
+    H = hadamard(tc.q)
+    rng = np.random.default_rng(5)
+
+    def sign(shape):
+        return np.where(rng.random(shape) < 0.5, -1.0, 1.0)
+
+    def exact_post(P, prior, jiggle_v2c=False):
+        p_in = np.maximum(P @ H, 0.0) / tc.q
+        v2c = var_to_check(tc, prior, p_in)
+        if jiggle_v2c:
+            Y = fourier(v2c)
+            Y = Y / Y[..., :1] + sign(Y.shape) * 2.0 ** -22
+            Y[..., 0] = 1.0
+            v2c = Y @ H / tc.q
+        return tentative(tc, prior, check_to_var(tc, v2c)).post
+
     for i in (0, 1):
-        out = D.round_step(gcode, L, _dev(to_state(c2vs[i])), "fused")
+        words = to_state(c2vs[i])
+        out = D.round_step(gcode, L, _dev(words), "fused")
         got = D.posterior(gcode, L, out["c2v"]).cpu().numpy()
-        ref = tentative(tc, p0, c2vs[i + 1]).post
-        print(f"  GPU round {i + 2}: {_metrics(got, ref)}", flush=True)
-        # FP32 tolerance on posteriors: 1e-4 of the symbol's largest
-        # probability for 99.9% of the symbols; the rest are symbols whose
-        # variable-to-check normalisation divides by a small Y(0) (prior and
-        # message disagree), where FP32 cancellation in the transform reaches
-        # ~1.5e-4 (bounded here by 1e-3).
-        assert _rel_err(got, ref, 0.999) < TOL_FP32
-        assert _rel_err(got, ref) < 10 * TOL_FP32
+        P = from_state(words)
+        ref = exact_post(P, p0)
+        moved = exact_post(P * (1 + sign(P.shape) * 2.0 ** -22), p0 * (1 + sign(p0.shape) * 2.0 ** -22), True)
+        cond = np.abs(moved - ref).max(-1) / ref.max(-1)
+        well = cond < 1e-5
+        err = np.abs(got - ref).max(-1) / ref.max(-1)
+        ill = err[~well]
+        print(f"  GPU round {i + 2}: {_metrics(got, ref)}; well-conditioned {well.sum()}/{well.size} symbols, "
+              f"max rel err on them {err[well].max():.2e}; ill-conditioned: max rel err {ill.max() if ill.size else 0:.2e}",
+              flush=True)
+        assert well.mean() > 0.9
+        assert err[well].max() < TOL_FP32
+        assert err.max() < 1e-2
     gcode.close()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("case", [CASES[0], CASES[5], CASES[7]], ids=lambda c: c[0])
 def test_decode_posterior_at_stopping_round(case, prec):
     name, m, k, N, F, ebn0 = case
@@ -92,11 +128,14 @@ def test_decode_posterior_at_stopping_round(case, prec):
           f"{_metrics(post[sel], ref.post[sel])}", flush=True)
     # the posterior's symbol decision is the oracle's
     assert np.array_equal(post[sel].argmax(-1), ref.post[sel].argmax(-1))
-    # errors compound over the rounds of a decode; FP16 storage adds a
-    # rounding of every message word per round
+    # errors compound over the rounds of a decode.  16-bit storage rounds
+    # every stored probability to a relative u (2^-11 FP16, 2^-8 BF16) each
+    # round; the posterior multiplies two stored messages, so the median L1
+    # distance is held to 4 u, the worst symbol to 40 u (FP32: 1e-4 and 1e-2)
     l1 = np.abs(post[sel] - ref.post[sel]).sum(-1)
-    tol = {"fp32": 1e-4, "fp16": 1e-2}[prec]
-    assert np.median(l1) < tol and l1.max() < 100 * tol
+    med, worst = {"fp32": (1e-4, 1e-2), "fp16": (4 * 2.0 ** -11, 40 * 2.0 ** -11),
+                  "bf16": (4 * 2.0 ** -8, 40 * 2.0 ** -8)}[prec]
+    assert np.median(l1) < med and l1.max() < worst
     gcode.close()
 
 
