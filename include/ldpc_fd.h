@@ -360,6 +360,16 @@ int32_t ldpc_fd_pool_submit(ldpc_fd_pool pool, int32_t code, const float *llr, i
  * time.  Asynchronous.  Errors: E_INVALID, E_UNSUPPORTED, E_HIP. */
 int32_t ldpc_fd_pool_step(ldpc_fd_pool pool, int32_t passes);
 
+/* How a step's per-code branches are ordered.  schedule 0 (default): every
+ * code's passes run on its own stream, all concurrently.  schedule 1
+ * (staggered): the code with the most work per pass (admitted-but-unharvested
+ * frames times the bytes of one of its frame-rounds) starts once every other
+ * code has run `lead` (0..1000) passes of the step; the rest overlaps.  With a
+ * code that fills the GPU alone, concurrency only adds interference, while
+ * the other codes' last passes (a few frames, latency-bound) still overlap
+ * with it.  Results do not depend on the schedule.  Errors: E_INVALID. */
+int32_t ldpc_fd_pool_set_schedule(ldpc_fd_pool pool, int32_t schedule, int32_t lead);
+
 /* Collect up to cap stopped frames of code `code` (synchronises the pool's
  * stream): tags[cap], iters[cap], status[cap] (LDPC_FD_STATUS_* bits) and
  * hard[cap][N] (host arrays; any may be NULL).  Their slots become free.

@@ -63,6 +63,7 @@ _SIGS = {
     "ldpc_fd_pool_create_budget": (_i32, [ctypes.POINTER(_c_void_p), _i32, _i64, _i32, _c_void_p,
                                           ctypes.POINTER(_c_void_p)]),
     "ldpc_fd_decode_ex": (_i32, [_c_void_p, _c_void_p, _c_void_p]),
+    "ldpc_fd_pool_set_schedule": (_i32, [_c_void_p, _i32, _i32]),
     "ldpc_fd_run_rounds": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _i32, _c_void_p, _c_void_p, _c_void_p,
                                   _c_void_p, _i32, _i32, _c_void_p]),
 }
@@ -400,6 +401,11 @@ class Pool:
         _check(lib().ldpc_fd_pool_submit(self.handle, k, _ptr(llr), n,
                                          None if t is None else t.ctypes.data, int(max_iter), ctypes.byref(got)))
         return got.value
+
+    def set_schedule(self, schedule: int, lead: int = 0):
+        """0: every code's passes concurrently; 1: the heaviest code starts after
+        the others' first `lead` passes (ldpc_fd_pool_set_schedule)."""
+        _check(lib().ldpc_fd_pool_set_schedule(self.handle, int(schedule), int(lead)))
 
     def step(self, passes: int = 1):
         _check(lib().ldpc_fd_pool_step(self.handle, int(passes)))

@@ -80,6 +80,11 @@ def serve(banks, offered_fps: float, duration_s: float, prec: str = "fp16", max_
     With `record`, the result also lists (code, Eb/N0 index, bank frame,
     iterations, hard decision) for every returned frame."""
     rng = np.random.default_rng(seed)
+    # each code's autotuned launch choices for a batch of its slot count (the
+    # pool captures its steps with the codes' tuning at that time)
+    from . import autotune
+    for b, n in zip(banks, slots_for_budget(banks, hbm_budget, prec)):
+        autotune.apply(b.gcode, prec, n)
     pool = D.Pool([b.gcode for b in banks], None, prec=prec, hbm_budget=hbm_budget)
     slots = pool.slots
     ncodes = len(banks)

@@ -65,8 +65,11 @@ def test_uneven_three_code_batch_in_one_pool_equals_each_code_alone():
         autotune.apply(c, "fp32", b.llr.shape[0])
     llrs = [_dev(b.llr) for b in batches]
     pool = D.Pool(codes, [b.llr.shape[0] for b in batches], prec="fp32")
-    # one launch of every pass, and steps of 4 passes with host reads between
+    # one launch of every pass (concurrent and staggered schedules), and steps
+    # of 4 passes with host reads between
     runs = [serving.decode_mixed(pool, llrs, 100), serving.decode_mixed(pool, llrs, 100, 4)]
+    pool.set_schedule(1, 16)
+    runs.append(serving.decode_mixed(pool, llrs, 100))
     pool.close()
     for i, (c, b, l) in enumerate(zip(codes, batches, llrs)):
         alone = {k: v.cpu().numpy() for k, v in D.decode(c, l, 100).items()}
