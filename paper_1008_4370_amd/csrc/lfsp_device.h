@@ -7,7 +7,8 @@
 // so each lane owns runs of 4 consecutive z (one 16-byte FP32 load), z bits
 // 0-1 and the high bits live in registers and bits 2..2+log2(L)-1 across the
 // frame's lanes.  Butterflies along register bits are plain VALU; along lane
-// bits they use DPP quad permutes (lane xor 1, 2) or ds_swizzle (xor 4..16).
+// bits they use DPP quad permutes (lane xor 1, 2), a DPP row rotation (xor 8)
+// or ds_swizzle (xor 4, 16).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -66,12 +67,15 @@ __device__ __forceinline__ float lane_xor(float v, int mask) {
 }
 
 // v[r] += c * v[r] of lane (this lane xor MASK), for all r: one
-// v_fmac_f32_dpp per register for quad-local masks (1, 2).  A single s_nop 1
+// v_fmac_f32_dpp per register for the masks DPP reaches within a row of 16
+// lanes (1, 2: quad permutes; 8: a rotation of the row by 8, which is lane
+// xor 8), the same single-rounding FMA as the generic form.  A single s_nop 1
 // ahead of the block covers the DPP read of a VGPR written by the preceding
 // VALU instruction; inside the block every instruction reads a register not
 // written earlier in the block.
 #define LFD_DPP1 "quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf\n"
 #define LFD_DPP2 "quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf\n"
+#define LFD_DPP8 "row_ror:8 row_mask:0xf bank_mask:0xf\n"
 #define LFD_F(i, c, D) "v_fmac_f32_dpp %" #i ", %" #i ", %" #c " " D
 #define LFD_BLK4(c, D) LFD_F(0, c, D) LFD_F(1, c, D) LFD_F(2, c, D) LFD_F(3, c, D)
 #define LFD_BLK8(c, D) LFD_BLK4(c, D) LFD_F(4, c, D) LFD_F(5, c, D) LFD_F(6, c, D) LFD_F(7, c, D)
@@ -85,18 +89,21 @@ __device__ __forceinline__ float lane_xor(float v, int mask) {
 
 template <int R>
 __device__ __forceinline__ void lane_fmac(float (&v)[R], float c, int mask) {
-  if (mask == 1 || mask == 2) {
+  if (mask == 1 || mask == 2 || mask == 8) {
     if constexpr (R == 4) {
       if (mask == 1) asm volatile("s_nop 1\n" LFD_BLK4(4, LFD_DPP1) : LFD_V4(v) : "v"(c));
-      else asm volatile("s_nop 1\n" LFD_BLK4(4, LFD_DPP2) : LFD_V4(v) : "v"(c));
+      else if (mask == 2) asm volatile("s_nop 1\n" LFD_BLK4(4, LFD_DPP2) : LFD_V4(v) : "v"(c));
+      else asm volatile("s_nop 1\n" LFD_BLK4(4, LFD_DPP8) : LFD_V4(v) : "v"(c));
       return;
     } else if constexpr (R == 8) {
       if (mask == 1) asm volatile("s_nop 1\n" LFD_BLK8(8, LFD_DPP1) : LFD_V8(v) : "v"(c));
-      else asm volatile("s_nop 1\n" LFD_BLK8(8, LFD_DPP2) : LFD_V8(v) : "v"(c));
+      else if (mask == 2) asm volatile("s_nop 1\n" LFD_BLK8(8, LFD_DPP2) : LFD_V8(v) : "v"(c));
+      else asm volatile("s_nop 1\n" LFD_BLK8(8, LFD_DPP8) : LFD_V8(v) : "v"(c));
       return;
     } else if constexpr (R == 16) {
       if (mask == 1) asm volatile("s_nop 1\n" LFD_BLK16(16, LFD_DPP1) : LFD_V16(v) : "v"(c));
-      else asm volatile("s_nop 1\n" LFD_BLK16(16, LFD_DPP2) : LFD_V16(v) : "v"(c));
+      else if (mask == 2) asm volatile("s_nop 1\n" LFD_BLK16(16, LFD_DPP2) : LFD_V16(v) : "v"(c));
+      else asm volatile("s_nop 1\n" LFD_BLK16(16, LFD_DPP8) : LFD_V16(v) : "v"(c));
       return;
     }
   }

@@ -777,7 +777,8 @@ __global__ __launch_bounds__(256, 2) void k_fused(DevCode cd, const float* __res
 // sums the check's magnitudes in edge order (the order of fused_item, so the
 // results are bit-identical to k_fused) and forms its own extrinsic output.
 // A check's latency is then one edge instead of k.  LDS: per wavefront T rows
-// of Q floats for the label permutations, and the stash [KMAX][T][Q].
+// of Q floats for the label permutations, and the stash [KMAX][T][Q], whose
+// first rows then hold the check's sums.
 template <class G, int KMAX, typename S, int AR>
 __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const float* __restrict__ tp,
                                                            S* __restrict__ buf0, S* __restrict__ buf1,
@@ -894,26 +895,61 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
       lds_put<G>(stash, rb, cf, zl, st);
     }
     __syncthreads();
+    // The check's sums, once per workgroup: every thread takes a share of the
+    // stash entries and adds the magnitudes (XORs the sign words) over the
+    // edges in edge order, as fused_item does, so the sums are bit-identical.
+    // They replace the stash in place: entry x of stash rows 0, 1 (and 2)
+    // takes the magnitude's (low) word, the sign word (and the FP64
+    // magnitude's high word); only the thread of entry x touches them.  The
+    // frames of a workgroup are the same for all its wavefronts, so any_write
+    // is uniform over the workgroup.
+    constexpr int TQ = G::T * G::QP;
+    uint32_t* su = reinterpret_cast<uint32_t*>(stash);
+    if (any_write) {
+      for (int x = threadIdx.x; x < TQ; x += blockDim.x) {
+        Acc m = 0;
+        uint32_t sg = 0u;
+        for (int i = 0; i < deg; ++i) {
+          const float w = stash[i * TQ + x];
+          m += (Acc)__builtin_fabsf(w);
+          sg ^= __float_as_uint(w);
+        }
+        if constexpr (P) {
+          const uint64_t mb = (uint64_t)__double_as_longlong(m);
+          su[x] = (uint32_t)mb;
+          su[2 * TQ + x] = (uint32_t)(mb >> 32);
+        } else {
+          su[x] = __float_as_uint(m);
+        }
+        su[TQ + x] = sg;
+      }
+    }
+    __syncthreads();
     if (j < deg && any_write) {
       Acc smag[G::R];
       uint32_t ssgn[G::R];
 #pragma unroll
-      for (int r = 0; r < G::R; ++r) {
-        smag[r] = 0;
-        ssgn[r] = 0u;
-      }
-      for (int i = 0; i < deg; ++i) {
-        const int rbi = (i * G::T + fl) * G::QP;
+      for (int h4 = 0; h4 < G::R / 4; ++h4) {
+        const int x = fl * G::QP + (((zl << 2) | (h4 << (2 + G::LOGL))) ^ cf);
+        const uint4 lo = *reinterpret_cast<const uint4*>(su + x);
+        const uint4 sg = *reinterpret_cast<const uint4*>(su + TQ + x);
+        const uint32_t l4[4] = {lo.x, lo.y, lo.z, lo.w};
+        const uint32_t s4[4] = {sg.x, sg.y, sg.z, sg.w};
+        uint32_t h4w[4] = {0u, 0u, 0u, 0u};
+        if constexpr (P) {
+          const uint4 hi = *reinterpret_cast<const uint4*>(su + 2 * TQ + x);
+          h4w[0] = hi.x;
+          h4w[1] = hi.y;
+          h4w[2] = hi.z;
+          h4w[3] = hi.w;
+        }
 #pragma unroll
-        for (int h4 = 0; h4 < G::R / 4; ++h4) {
-          const int z0 = (zl << 2) | (h4 << (2 + G::LOGL));
-          const float4 w = *reinterpret_cast<const float4*>(stash + (rbi | (z0 ^ cf)));
-          const float ww[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-          for (int q4 = 0; q4 < 4; ++q4) {
-            smag[4 * h4 + q4] += (Acc)__builtin_fabsf(ww[q4]);
-            ssgn[4 * h4 + q4] ^= __float_as_uint(ww[q4]);
-          }
+        for (int q4 = 0; q4 < 4; ++q4) {
+          ssgn[4 * h4 + q4] = s4[q4];
+          if constexpr (P)
+            smag[4 * h4 + q4] = __longlong_as_double((long long)(((uint64_t)h4w[q4] << 32) | l4[q4]));
+          else
+            smag[4 * h4 + q4] = __uint_as_float(l4[q4]);
         }
       }
       const int e = e0 + j;
