@@ -266,6 +266,19 @@ __device__ __forceinline__ void normalise_gamma_d(const double (&y)[G::R], float
 // which is the butterfly output negated on the lanes whose bit is set; the
 // flips of later stages factor out because both members of every later pair
 // share the bit.  Products of two such transforms carry s(z)^2 = 1.
+//
+// Lane-reversed input: in a vector held lane-reversed, lane zl of a frame
+// holds the entries of lane zl ^ (L - 1), i.e. x'(y) = x(y ^ m) with m the mask
+// of the lane bits of the index, and s(z) = (-1)^(z.m).  Then wht_s(x') =
+// s(z) sum_y x(y ^ m) (-1)^(z.y) = s(z)^2 V(z) = V(z): the exact transform, with
+// no sign to undo.  Loads and LDS gathers produce the reversed layout at no
+// cost (the lane's addresses use lane_rev(zl)); the transform's output is in
+// the ordinary layout.
+template <class G>
+__device__ __forceinline__ int lane_rev(int zl) {
+  return zl ^ (G::L - 1);
+}
+
 template <class G>
 __device__ __forceinline__ void wht_s(float (&v)[G::R], int zl) {
 #pragma unroll
@@ -292,7 +305,9 @@ __device__ __forceinline__ void wht_s(float (&v)[G::R], int zl) {
 // (a wave-uniform 8-byte word, byte b).  `rb` is the element index of this
 // lane's frame row, `cf` the frame's swizzle.  A z = A z_reg ^ A z_lane, so a
 // read index is (rb | (A z_lane ^ cf)) ^ A z_reg: one XOR per element with a
-// wave-uniform A z_reg.  Lanes of one frame exchange entries through the row;
+// wave-uniform A z_reg.  The values are written from lane zl's entries; the
+// read side forms the entries of lane zr (zl, or lane_rev(zl) for a
+// lane-reversed result).  Lanes of one frame exchange entries through the row;
 // LDS operations of a wave execute in order, and wave barriers keep the
 // compiler from moving a lane's accesses across the exchange.
 typedef __attribute__((address_space(3))) const float lds_float;
@@ -312,14 +327,15 @@ __device__ __forceinline__ void lds_put(float* lds, int rb, int cf, int zl, cons
 }
 
 template <class G>
-__device__ __forceinline__ void permute(float (&v)[G::R], float* lds, int rb, int cf, int zl, uint64_t cols) {
+__device__ __forceinline__ void permute(float (&v)[G::R], float* lds, int rb, int cf, int zl, uint64_t cols,
+                                       int zr) {
   __builtin_amdgcn_wave_barrier();
   lds_put<G>(lds, rb, cf, zl, v);
   __builtin_amdgcn_wave_barrier();
   int pl = 0;
 #pragma unroll
   for (int lb = 0; lb < G::LOGL; ++lb)
-    if ((zl >> lb) & 1) pl ^= (int)((cols >> (8 * (2 + lb))) & 0xFF);
+    if ((zr >> lb) & 1) pl ^= (int)((cols >> (8 * (2 + lb))) & 0xFF);
   // LDS byte address of the row entry, so each gathered element costs one XOR.
   // Rows start at multiples of 4Q bytes from the array base, which is itself
   // 4Q-aligned (the array is the kernel's only LDS), so XOR-ing an offset
@@ -336,6 +352,13 @@ __device__ __forceinline__ void permute(float (&v)[G::R], float* lds, int rb, in
     v[r] = *reinterpret_cast<const lds_float*>((size_t)(lbase4 ^ (pr << 2)));
   }
   __builtin_amdgcn_wave_barrier();
+}
+
+// The gather into the ordinary layout (zr = zl); with zr = lane_rev(zl) the
+// result is lane-reversed.
+template <class G>
+__device__ __forceinline__ void permute(float (&v)[G::R], float* lds, int rb, int cf, int zl, uint64_t cols) {
+  permute<G>(v, lds, rb, cf, zl, cols, zl);
 }
 
 // ---- message storage ------------------------------------------------------------

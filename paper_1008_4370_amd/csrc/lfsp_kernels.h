@@ -56,15 +56,18 @@ __device__ __forceinline__ void prior_coeffs(const float* llr_fv, float (&t)[G::
 // the first two transforms cancel in the product; the third is undone with
 // s(z) before the values are written to the frame's LDS row, from which the
 // 3m points are read.
-// Signs of Q(z) = s(z) A(z) (A as wht_s returns it) at the 3m read points:
-// e_i (bitwise-MAP bits) and M_h^T e_i for the two edges of the variable
-// (cols_a, cols_b), read back through the frame's LDS row.
-template <class G>
+// Signs of Q(z) = s(z) A(z) (A as wht_s returns it; A = Q when the
+// transform's input was lane-reversed, LANE_SIGNS = false) at the 3m read
+// points: e_i (bitwise-MAP bits) and M_h^T e_i for the two edges of the
+// variable (cols_a, cols_b), read back through the frame's LDS row.
+template <class G, bool LANE_SIGNS = true>
 __device__ __forceinline__ void decide_signs(float (&A)[G::R], float* lds, int rb, int cf, int zl, uint64_t cols_a,
                                              uint64_t cols_b, int& hard, int& fa, int& fb) {
-  const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
+  if constexpr (LANE_SIGNS) {
+    const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
 #pragma unroll
-  for (int r = 0; r < G::R; ++r) A[r] *= sz;
+    for (int r = 0; r < G::R; ++r) A[r] *= sz;
+  }
   __builtin_amdgcn_wave_barrier();
   lds_put<G>(lds, rb, cf, zl, A);
   __builtin_amdgcn_wave_barrier();
@@ -98,20 +101,23 @@ __device__ __forceinline__ void decide(const float (&Y)[G::R], float (&Xo)[G::R]
 // the posterior pmf is pp . x_c with x_c the own message's pmf (inverse
 // transform of Xo, clamped at zero likewise), one transform back gives Q.
 // Two Hadamard transforms instead of three.  Xo is overwritten.
-template <class G>
+// REV: Xo is held lane-reversed (lane_rev), so its transform carries no lane
+// signs.
+template <class G, bool REV = false>
 __device__ __forceinline__ void decide_pmf(const float (&pp)[G::R], float (&Xo)[G::R], float* lds, int rb, int cf,
                                            int zl, uint64_t cols_a, uint64_t cols_b, int& hard, int& fa, int& fb) {
-  const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
+  const float sz = (!REV && (__builtin_popcount(zl) & 1)) ? -1.0f : 1.0f;
   wht_s<G>(Xo, zl);
 #pragma unroll
-  for (int r = 0; r < G::R; ++r) Xo[r] = __builtin_fmaxf(Xo[r] * sz, 0.0f) * pp[r];
+  for (int r = 0; r < G::R; ++r) Xo[r] = __builtin_fmaxf(REV ? Xo[r] : Xo[r] * sz, 0.0f) * pp[r];
   wht_s<G>(Xo, zl);
   decide_signs<G>(Xo, lds, rb, cf, zl, cols_a, cols_b, hard, fa, fb);
 }
 
 // The same decision when the own message arrives as its pmf (16-bit storage,
 // kPmfWords): the posterior pmf is pp . xo directly, one transform gives Q.
-// xo is overwritten.
+// pp and xo are held lane-reversed (lane_rev), so Q needs no sign fix.  xo is
+// overwritten.
 template <class G>
 __device__ __forceinline__ void decide_pmf_direct(const float (&pp)[G::R], float (&xo)[G::R], float* lds, int rb,
                                                   int cf, int zl, uint64_t cols_a, uint64_t cols_b, int& hard,
@@ -119,7 +125,7 @@ __device__ __forceinline__ void decide_pmf_direct(const float (&pp)[G::R], float
 #pragma unroll
   for (int r = 0; r < G::R; ++r) xo[r] *= pp[r];
   wht_s<G>(xo, zl);
-  decide_signs<G>(xo, lds, rb, cf, zl, cols_a, cols_b, hard, fa, fb);
+  decide_signs<G, false>(xo, lds, rb, cf, zl, cols_a, cols_b, hard, fa, fb);
 }
 
 // ---- tentative decision on the matrix cores ------------------------------------
@@ -471,21 +477,26 @@ __device__ __forceinline__ void issue_edge(const DevCode& cd, const float* __res
 // the frame errors that the Fourier-domain form adds over the FP64 oracle.
 // First half: v := p0 . max(x, 0), x the inverse transform of V (the product
 // pmf, up to a positive factor).
-template <class G>
+// REV: v is held lane-reversed (lane_rev), so its transform carries no lane
+// signs; pr and the result are in the ordinary layout.
+template <class G, bool REV = false>
 __device__ __forceinline__ void symbol_prior_product(float (&v)[G::R], const float (&pr)[G::R], int zl) {
-  const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
+  const float sz = (!REV && (__builtin_popcount(zl) & 1)) ? -1.0f : 1.0f;
   wht_s<G>(v, zl);
 #pragma unroll
-  for (int r = 0; r < G::R; ++r) v[r] = __builtin_fmaxf(v[r] * sz, 0.0f) * pr[r];
+  for (int r = 0; r < G::R; ++r) v[r] = __builtin_fmaxf(REV ? v[r] : v[r] * sz, 0.0f) * pr[r];
 }
 
-// Second half: back to the Fourier domain.
-template <class G>
+// Second half: back to the Fourier domain (REV: v lane-reversed, no sign to
+// undo).
+template <class G, bool REV = false>
 __device__ __forceinline__ void symbol_prior_back(float (&v)[G::R], int zl) {
-  const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
   wht_s<G>(v, zl);
+  if constexpr (!REV) {
+    const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
 #pragma unroll
-  for (int r = 0; r < G::R; ++r) v[r] *= sz;
+    for (int r = 0; r < G::R; ++r) v[r] *= sz;
+  }
 }
 
 template <class G>
@@ -555,15 +566,33 @@ __device__ __forceinline__ float check_output(Acc smag, uint32_t ssgn, float own
 // The check node's output (variable coordinates, as check_output forms it) in
 // the storage's word format: unchanged for FP32 storage; for 16-bit storage
 // the message pmf times q, the transform of P with its negative rounding
-// residue set to zero.
+// residue set to zero.  For 16-bit storage o arrives lane-reversed (gathered
+// with lane_rev, see out_lane), so the transform needs no sign fix, and leaves
+// in the ordinary layout.
 template <class G, typename S>
 __device__ __forceinline__ void to_storage_word(float (&o)[G::R], int zl) {
   if constexpr (kPmfWords<S>) {
-    const float sz = (__builtin_popcount(zl) & 1) ? -1.0f : 1.0f;
     wht_s<G>(o, zl);
 #pragma unroll
-    for (int r = 0; r < G::R; ++r) o[r] = __builtin_fmaxf(o[r] * sz, 0.0f);
+    for (int r = 0; r < G::R; ++r) o[r] = __builtin_fmaxf(o[r], 0.0f);
   }
+}
+
+// Lane whose entries the inverse label permutation gathers into this lane:
+// lane-reversed for 16-bit storage (to_storage_word transforms the result).
+template <class G, typename S>
+__device__ __forceinline__ int out_lane(int zl) {
+  return kPmfWords<S> ? lane_rev<G>(zl) : zl;
+}
+
+// Lane whose message entries and channel pmf the variable node of the default
+// arithmetic (kProbPrior) loads and forms: lane-reversed, so that the first
+// transform of each incoming message carries no lane signs (16-bit storage:
+// the product pmf's transform back and the decision's transform; FP32
+// storage: the transforms of the two loaded Fourier-domain messages).
+template <class G, int AR>
+__device__ __forceinline__ int in_lane(int zl) {
+  return AR == kProbPrior ? lane_rev<G>(zl) : zl;
 }
 
 // P (precise): the variable node in FP64 (prior factors given as signed
@@ -604,7 +633,8 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
   constexpr bool TWO = KMAX <= 8 && AR == kProbPrior && (G::LOGQ <= 6 || G::LOGR <= 3);
   constexpr bool PACK = KMAX <= 8;
   EdgeLoads<G, S, PACK> eb[TWO ? 2 : 1];
-  issue_edge<G, S, AR, PACK>(cd, tp, cin, fb, f, e0, fs, any_decide, zl, eb[0]);
+  const int zx = in_lane<G, AR>(zl);   // lane whose message entries this lane loads
+  issue_edge<G, S, AR, PACK>(cd, tp, cin, fb, f, e0, fs, any_decide, zx, eb[0]);
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) {
     if (j < deg) {
@@ -612,7 +642,7 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
       const int bc = TWO ? (j & 1) : 0, bn = TWO ? ((j + 1) & 1) : 0;
       const EdgeLoads<G, S, PACK> cur0 = eb[bc];
       const EdgeLoads<G, S, PACK>& cur = TWO ? eb[bc] : cur0;
-      if (j + 1 < deg) issue_edge<G, S, AR, PACK>(cd, tp, cin, fb, f, e + 1, fs, any_decide, zl, eb[bn]);
+      if (j + 1 < deg) issue_edge<G, S, AR, PACK>(cd, tp, cin, fb, f, e + 1, fs, any_decide, zx, eb[bn]);
       const int v = uni(cd.e_var[e]);
       const int eo = uni(cd.e_other[e]);
       const int h = uni(cd.e_label[e]);
@@ -628,9 +658,10 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
         for (int r = 0; r < G::R; ++r) st[j][r] = (float)y64[r];
       } else if constexpr (kPmfWords<S>) {
         // the stored word is the other message's pmf (times q): the product
-        // with the channel pmf needs no transform
+        // with the channel pmf needs no transform (both lane-reversed, as
+        // the loads)
         float pr[G::R];
-        prob_prior<G>(t, zl, pr);
+        prob_prior<G>(t, zx, pr);
         if (any_first) {
 #pragma unroll
           for (int r = 0; r < G::R; ++r) st[j][r] = fs.first ? pr[r] : pr[r] * cur.x(r);
@@ -651,17 +682,17 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
             fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
           }
         }
-        symbol_prior_back<G>(st[j], zl);
+        symbol_prior_back<G, true>(st[j], zl);
       } else {
 #pragma unroll
         for (int r = 0; r < G::R; ++r)
-          st[j][r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x(r));
+          st[j][r] = fs.first ? ((r == 0 && zx == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x(r));
         if constexpr (AR == kSymbolPrior) {
           conv_symbol_prior<G>(st[j], cur.pr, zl);
         } else if constexpr (AR == kProbPrior) {
           float pr[G::R];
           prob_prior<G>(t, zl, pr);
-          symbol_prior_product<G>(st[j], pr, zl);
+          symbol_prior_product<G, true>(st[j], pr, zl);   // st[j] loaded lane-reversed
           // owner visit: the decision from the product pmf before the
           // transform back (decide_pmf)
           if (any_decide && e < eo) {
@@ -670,7 +701,7 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
             for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o(r));
             int hd, fa, fo;
             const int ho = uni(cd.e_label[eo]);
-            decide_pmf<G>(st[j], xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
+            decide_pmf<G, true>(st[j], xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
             if (valid && fs.decide && zl == 0) {
               hard[(size_t)f * cd.N + v] = (uint8_t)hd;
               fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
@@ -726,7 +757,7 @@ __device__ __forceinline__ void fused_item(const DevCode& cd, const float* __res
       float o[G::R];
 #pragma unroll
       for (int r = 0; r < G::R; ++r) o[r] = check_output<S, Acc>(smag[r], ssgn[r], st[j][r]);
-      permute<G>(o, lds, rb, cf, zl, uni64(cd.colsT[hinv]));
+      permute<G>(o, lds, rb, cf, zl, uni64(cd.colsT[hinv]), out_lane<G, S>(zl));
       to_storage_word<G, S>(o, zl);
       if (valid && fs.write) store_msg<G, S>(cout + fb + (size_t)e * G::Q, zl, o);
     }
@@ -814,7 +845,8 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
     if (j < deg) {
       const int e = e0 + j;
       EdgeLoads<G, S, true> cur;
-      issue_edge<G, S, AR, true>(cd, tp, cin, fb, f, e, fs, any_decide, zl, cur);
+      const int zx = in_lane<G, AR>(zl);   // lane whose message entries this lane loads
+      issue_edge<G, S, AR, true>(cd, tp, cin, fb, f, e, fs, any_decide, zx, cur);
       const int v = uni(cd.e_var[e]);
       const int eo = uni(cd.e_other[e]);
       const int h = uni(cd.e_label[e]);
@@ -830,7 +862,7 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
         for (int r = 0; r < G::R; ++r) st[r] = (float)y64[r];
       } else if constexpr (kPmfWords<S>) {
         float pr[G::R];
-        prob_prior<G>(t, zl, pr);
+        prob_prior<G>(t, zx, pr);   // lane-reversed, as the loads
 #pragma unroll
         for (int r = 0; r < G::R; ++r) st[r] = fs.first ? pr[r] : pr[r] * cur.x(r);
         if (any_decide && e < eo) {
@@ -846,23 +878,23 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
             fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
           }
         }
-        symbol_prior_back<G>(st, zl);
+        symbol_prior_back<G, true>(st, zl);
       } else {
 #pragma unroll
-        for (int r = 0; r < G::R; ++r) st[r] = fs.first ? ((r == 0 && zl == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x(r));
+        for (int r = 0; r < G::R; ++r) st[r] = fs.first ? ((r == 0 && zx == 0) ? 1.0f : 0.0f) : gamma_inv(cur.x(r));
         if constexpr (AR == kSymbolPrior) {
           conv_symbol_prior<G>(st, cur.pr, zl);
         } else if constexpr (AR == kProbPrior) {
           float pr[G::R];
           prob_prior<G>(t, zl, pr);
-          symbol_prior_product<G>(st, pr, zl);
+          symbol_prior_product<G, true>(st, pr, zl);   // st loaded lane-reversed
           if (any_decide && e < eo) {
             float xo[G::R];
 #pragma unroll
             for (int r = 0; r < G::R; ++r) xo[r] = gamma_inv(cur.o(r));
             int hd, fa, fo;
             const int ho = uni(cd.e_label[eo]);
-            decide_pmf<G>(st, xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
+            decide_pmf<G, true>(st, xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
             if (valid && fs.decide && zl == 0) {
               hard[(size_t)f * cd.N + v] = (uint8_t)hd;
               fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
@@ -957,7 +989,7 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
       float o[G::R];
 #pragma unroll
       for (int r = 0; r < G::R; ++r) o[r] = check_output<S, Acc>(smag[r], ssgn[r], st[r]);
-      permute<G>(o, lds, rb, cf, zl, uni64(cd.colsT[hinv]));
+      permute<G>(o, lds, rb, cf, zl, uni64(cd.colsT[hinv]), out_lane<G, S>(zl));
       to_storage_word<G, S>(o, zl);
       if (valid && fs.write) store_msg<G, S>(cout + fb + (size_t)e * G::Q, zl, o);
     }
