@@ -323,6 +323,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--precise", action="store_true",
                     help="time the FP64 variable node (tuning key PRECISE) as the headline")
+    ap.add_argument("--butterfly", action="store_true",
+                    help="the FP32 butterfly variable node (tuning key PRECISE = 0; FP32 storage)")
+    ap.add_argument("--decision-mfma", action="store_true",
+                    help="with --butterfly: the decision's transforms as FP16 MFMAs (tuning key DECISION_MFMA = 1)")
     ap.add_argument("--no-logsp-variant", action="store_true",
                     help="skip timing the conventional log-domain SP decoder on the same batch")
     ap.add_argument("--no-precise-variant", action="store_true",
@@ -381,6 +385,9 @@ def main():
         code.set_tuning(**tune)
     if args.precise:
         code.set_tuning(precise=1)
+    if args.butterfly or args.decision_mfma:
+        code.set_tuning(precise=0, decision_mfma=int(args.decision_mfma))
+    default_form = not (args.precise or args.butterfly or args.decision_mfma)
     dec = D.Decoder(code, F, args.prec, args.mode)
     llr = torch.from_numpy(batch.llr).cuda()
     for _ in range(args.warmup):
@@ -414,7 +421,7 @@ def main():
         ms_var, _ = D.profile_read(D.K_VAR)
 
     precise_line = prob_line = None
-    if args.mode == "fused" and not args.precise and not args.no_precise_variant:
+    if args.mode == "fused" and default_form and not args.no_precise_variant:
         # The same batch with the other FP32 variable-node forms (FP32 storage;
         # 16-bit pmf words are read by the default form only): the FP64
         # variable node (tuning key PRECISE = 1, 8 entries per lane where the
@@ -456,7 +463,7 @@ def main():
         del ldec
 
     legs = None
-    if args.mode == "fused" and not args.precise and not args.no_legs:
+    if args.mode == "fused" and default_form and not args.no_legs:
         # The comparison the precision plan sets: the 16-bit-storage decoder
         # against the FP32 decoders on the same frames (the other storage type
         # of the fused decoder, and the PLAIN two-kernel FP32 decoder).
@@ -511,7 +518,7 @@ def main():
     # measured HBM bytes per k_fused launch (committed counters) for this exact
     # configuration: default workload, FP32 storage, fused, tuned defaults
     traffic, traffic_note = None, "no counters for this configuration"
-    if (args.workload == "gf64_n1000" and args.mode == "fused" and not args.precise
+    if (args.workload == "gf64_n1000" and args.mode == "fused" and default_form
             and not tune and args.point == 2 and args.max_iter == 100):
         t = measured_traffic(args.prec)
         if t is None:
