@@ -69,7 +69,7 @@ struct ldpc_fd_code_s {
   // Captured chunks of rounds of the fused decoder, keyed by everything their
   // kernel arguments depend on.
   struct GraphKey {
-    int F, prec, chunk, max_iter, logr, blocks, tail, ar, early;
+    int F, prec, chunk, max_iter, logr, blocks, tail, rgrid, ar, early;
     const void *ws, *llr, *hard, *synd, *iters, *status;
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
   };
@@ -267,6 +267,20 @@ void launch_syndrome(const ldpc_fd_code_s* c, int F, const uint8_t* hard, const 
     hipLaunchKernelGGL(k_syndrome, dim3(cdiv((long)F * c->M, 256)), dim3(256), 0, s, c->dev, hard, fsw, synd,
                        fsynd, unsat, mism, alist, nact, F, active, rnd);
   }
+}
+
+// Largest active count for which a pass's syndromes and retirement run as one
+// launch (k_syndrome_retire: each workgroup that checked a frame issues a
+// device-scope release, cheap for a few frames, tens of microseconds for
+// thousands); above it the syndrome kernel and k_retire_compact.
+constexpr int kRetireOneLaunchMax = 128;
+
+// Workgroups of the one-launch form for a code with F frame slots whose pass
+// starts with `left` active frames in the tail form, or 0 for the two-launch
+// form.
+int retire_grid(const ldpc_fd_code_s* c, int F, bool tail, int left) {
+  if (!tail || left > kRetireOneLaunchMax) return 0;
+  return std::max(1, std::min({F, std::max(c->tail_frames, 1), kRetireOneLaunchMax}));
 }
 
 // Syndromes of the active frames, stopping rule and compaction.  tail_grid > 0
@@ -612,7 +626,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   const int ar = prior ? kSymbolPrior : var_form(c->precise);
   // One pass over the active frames (each at its own round, see k_fused),
   // syndromes of the decisions it formed, stopping rule and compaction.
-  auto enqueue_round = [&](hipStream_t st, hipEvent_t e0, hipEvent_t e1, int lr, bool tail) {
+  auto enqueue_round = [&](hipStream_t st, hipEvent_t e0, hipEvent_t e1, int lr, bool tail, int rgrid) {
     bool ok = true;
     if (e0) (void)hipEventRecord(e0, st);
     const bool split = tail && c->split;
@@ -621,7 +635,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     ok = run_fused(c, lr, fa, st);
     if (e1) (void)hipEventRecord(e1, st);
     launch_syndrome_retire(c, F, hard, w.fsw, synd, w.unsat, w.mism, w.alist, w.nact, w.rnd, max_iter, nullptr, w.tmp,
-                           iters, status, nullptr, nullptr, tail ? std::max(c->tail_frames, 1) : 0, st, early);
+                           iters, status, nullptr, nullptr, rgrid, st, early);
     return ok;
   };
   // A frame needs at most max_iter + 1 passes (pass l forms round l's decision).
@@ -635,6 +649,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   if (!c->graphs || t_prof.on) {
     int lr = variant(F);
     bool tail = is_tail(F);
+    int rgrid = retire_grid(c, F, tail, F);
     for (int p = 1; p <= passes; ++p) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (t_prof.on) {
@@ -642,13 +657,14 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
         e1 = t_prof.get();
         if (e0 && e1) t_prof.ev[LDPC_FD_K_FUSED].emplace_back(e0, e1);
       }
-      if (!enqueue_round(s, e0, e1, lr, tail)) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+      if (!enqueue_round(s, e0, e1, lr, tail, rgrid)) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
       if (!async && (p % c->chunk == 0 || p == passes)) {
         int left = 0;
         if ((rc = read_count(w.nact, s, &left))) return rc;
         if (left == 0) break;
         lr = variant(left);
         tail = is_tail(left);
+        rgrid = retire_grid(c, F, tail, left);
       }
     }
     HIP_TRY(hipGetLastError());
@@ -659,7 +675,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   const int chunk = c->chunk;
   std::lock_guard<std::mutex> lock(c->gmu);
   // The captured chunk for kernel variant lr (found in or added to the cache).
-  auto chunk_graph = [&](int lr, bool tail, hipGraphExec_t* exec) -> int32_t {
+  auto chunk_graph = [&](int lr, bool tail, int rgrid, hipGraphExec_t* exec) -> int32_t {
     // zero-filled first: keys compare with memcmp, padding included
     ldpc_fd_code_s::GraphKey key;
     std::memset(&key, 0, sizeof key);
@@ -670,6 +686,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     key.logr = lr;
     key.blocks = c->blocks;
     key.tail = tail ? 1 : 0;
+    key.rgrid = rgrid;
     key.ar = ar;
     key.early = early;
     key.ws = workspace;
@@ -689,7 +706,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     bool ok = true;
-    for (int r = 0; r < chunk; ++r) ok = enqueue_round(c->cap_stream, nullptr, nullptr, lr, tail) && ok;
+    for (int r = 0; r < chunk; ++r) ok = enqueue_round(c->cap_stream, nullptr, nullptr, lr, tail, rgrid) && ok;
     HIP_TRY(hipStreamEndCapture(c->cap_stream, &graph));
     if (!ok) {
       (void)hipGraphDestroy(graph);
@@ -705,7 +722,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   int left = F;
   for (int p = 0; p < passes; p += chunk) {
     hipGraphExec_t exec = nullptr;
-    if ((rc = chunk_graph(variant(left), is_tail(left), &exec))) return rc;
+    if ((rc = chunk_graph(variant(left), is_tail(left), retire_grid(c, F, is_tail(left), left), &exec))) return rc;
     HIP_TRY(hipGraphLaunch(exec, s));
     if (async) continue;   // passes after the last frame stops find no active frame
     if ((rc = read_count(w.nact, s, &left))) return rc;
