@@ -193,16 +193,17 @@ def serve(banks, offered_fps: float, duration_s: float, prec: str = "fp16", max_
     return out
 
 
-def decode_mixed(pool: D.Pool, llrs, max_iter: int = 100, passes_per_step: int | None = None):
+def decode_mixed(pool: D.Pool, llrs, max_iter: int = 100, passes_per_step: int | None = 8):
     """Decode one batch per pool code together: every frame is admitted at
-    once (the pool needs as many slots as frames).  Default: one pool step of
-    max_iter + 1 passes, i.e. one graph launch that runs every pass of every
-    code on concurrent streams with no host read in between (a frame needs at
-    most max_iter + 1 passes; the passes after a code's frames have all
-    stopped find no active frame), then every code is harvested.  With
-    passes_per_step, steps of that many passes alternate with host reads of
-    the active counts, and a code is harvested (and left out of later steps)
-    as soon as none of its frames is active.  Returns, per code, dict(iters,
+    once (the pool needs as many slots as frames).  Steps of passes_per_step
+    passes (each one graph launch running every pass of every code with active
+    frames on concurrent streams) alternate with reads of the codes' active
+    counts, from which the next step picks each code's kernel forms (the
+    few-frames forms once a code's active count is within its tail threshold)
+    and leaves out codes with no active frame; a code is harvested as soon as
+    none of its frames is active.  passes_per_step=None: one step of
+    max_iter + 1 passes (a frame needs at most that many) with no host read in
+    between, then every code is harvested.  Returns, per code, dict(iters,
     status, hard) in frame order."""
     ncodes = len(llrs)
     for k, llr in enumerate(llrs):
@@ -225,15 +226,14 @@ def decode_mixed(pool: D.Pool, llrs, max_iter: int = 100, passes_per_step: int |
         for k in range(ncodes):
             harvest(k)
         return got
-    # a code whose frames have all stopped is harvested at once, which takes it
-    # out of the following steps
-    for _ in range((max_iter + passes_per_step) // passes_per_step + 1):
-        pool.step(passes_per_step)
+    passes = 0
+    while passes < max_iter + 1:
+        n = min(passes_per_step, max_iter + 1 - passes)
+        pool.step(n)
+        passes += n
         for k in range(ncodes):
             if got[k] is None and pool.active(k) == 0:
                 harvest(k)
         if all(g is not None for g in got):
-            break
-    else:
-        raise RuntimeError("frames still active after max_iter + 1 passes")
-    return got
+            return got
+    raise RuntimeError("frames still active after max_iter + 1 passes")

@@ -55,9 +55,11 @@ def test_gf256_n512_8192_frames_per_storage_type():
 
 def test_uneven_three_code_batch_in_one_pool_equals_each_code_alone():
     """3000 x GF(16) N=2048 + 6000 x GF(64) N=512 + 2000 x GF(256) k=16 N=256 at
-    2.5 dB decoded together in one pool, as one step of every pass (one graph
-    launch) and as steps of 4 passes (one graph replay per step runs every
-    code): per-frame results equal those of each code's batch decoded alone."""
+    2.5 dB decoded together in one pool, as steps of 8 passes (the default:
+    one graph replay per step runs every code, each code's kernel forms chosen
+    from its active count), steps of 4 passes, one step of every pass (one
+    graph launch) and staggered steps: per-frame results equal those of each
+    code's batch decoded alone."""
     batches = [synth.make_batch(w) for w in ("gf16_n2048", "gf64_n512", "gf256_n256_k16")]
     print("[case] mixed batch 11000 frames", flush=True)
     codes = [D.Code.from_synth(b.code) for b in batches]
@@ -65,11 +67,12 @@ def test_uneven_three_code_batch_in_one_pool_equals_each_code_alone():
         autotune.apply(c, "fp32", b.llr.shape[0])
     llrs = [_dev(b.llr) for b in batches]
     pool = D.Pool(codes, [b.llr.shape[0] for b in batches], prec="fp32")
-    # one launch of every pass (concurrent and staggered schedules), and steps
-    # of 4 passes with host reads between
-    runs = [serving.decode_mixed(pool, llrs, 100), serving.decode_mixed(pool, llrs, 100, 4)]
-    pool.set_schedule(1, 16)
+    runs = [serving.decode_mixed(pool, llrs, 100), serving.decode_mixed(pool, llrs, 100, 4),
+            serving.decode_mixed(pool, llrs, 100, None)]
+    pool.set_schedule(1, 4)
     runs.append(serving.decode_mixed(pool, llrs, 100))
+    pool.set_schedule(1, 16)
+    runs.append(serving.decode_mixed(pool, llrs, 100, None))
     pool.close()
     for i, (c, b, l) in enumerate(zip(codes, batches, llrs)):
         alone = {k: v.cpu().numpy() for k, v in D.decode(c, l, 100).items()}
