@@ -383,7 +383,7 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
 /* Tuning of a code object's kernels (results are identical for every setting
  * except LDPC_FD_TUNE_PRECISE and LDPC_FD_TUNE_DECISION_MFMA; only speed changes).  Set by the autotuner, read back for its cache.
  *   LDPC_FD_TUNE_LANE_ENTRIES: entries of a frame's 2^m-vector held per lane
- *     (4, 8 or 16; 16 needs m <= 7 and rows of weight <= 8).  Fewer entries
+ *     (4, 8 or 16; 16 needs m >= 4 and rows of weight <= 8).  Fewer entries
  *     per lane means more lanes per frame, fewer registers and more waves.
  *   LDPC_FD_TUNE_GRID_BLOCKS: workgroups of the grid-stride fused pass (>= 8).
  *   LDPC_FD_TUNE_CHUNK: rounds between host reads of the active-frame count.

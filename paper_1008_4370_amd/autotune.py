@@ -40,7 +40,7 @@ def lane_choices(m: int, kmax: int):
     out = [4]
     if kmax <= 16 and q >= 8:
         out.append(8)
-    if kmax <= 8 and 16 <= q <= 128:
+    if kmax <= 8 and q >= 16:
         out.append(16)
     return out
 

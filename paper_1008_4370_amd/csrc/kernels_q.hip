@@ -135,12 +135,12 @@ struct Impl {
 };
 
 // Kernel variant: rows of weight <= 8 have variants with 4, 8 or 16 entries
-// per lane (log2 R = 2, 3, 4; 16 entries only for q <= 128, where the kernel
-// keeps its stash in registers); rows of weight 9..16 use 4 or 8.
+// per lane (log2 R = 2, 3, 4; 16 entries for q >= 16); rows of weight 9..16
+// use 4 or 8.
 template <int LOGQ, class Fn>
 bool dispatch_q(int kmax, int logr, Fn&& fn) {
   if (kmax <= 8) {
-    if constexpr (LOGQ >= 4 && LOGQ <= 7) {
+    if constexpr (LOGQ >= 4) {
       if (logr == 4) return fn(Impl<LOGQ, 4, 8>{});
     }
     if constexpr (LOGQ >= 3) {

@@ -954,7 +954,7 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
   switch (key) {
     case LDPC_FD_TUNE_LANE_ENTRIES:
       if (value != 4 && value != 8 && value != 16) return fail(LDPC_FD_E_INVALID, "entries per lane: 4, 8 or 16");
-      if (value > c->q || (value == 16 && c->m == 8) || (value > 8 && c->kmax > 8))
+      if (value > c->q || (value > 8 && c->kmax > 8))
         return fail(LDPC_FD_E_UNSUPPORTED, "no kernel variant with that many entries per lane for this code");
       c->logr = value == 4 ? 2 : value == 8 ? 3 : 4;
       return LDPC_FD_OK;
@@ -972,7 +972,7 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
       return LDPC_FD_OK;
     case LDPC_FD_TUNE_TAIL_ENTRIES:
       if (value != 4 && value != 8 && value != 16) return fail(LDPC_FD_E_INVALID, "entries per lane: 4, 8 or 16");
-      if (value > c->q || (value == 16 && c->m == 8) || (value > 8 && c->kmax > 8))
+      if (value > c->q || (value > 8 && c->kmax > 8))
         return fail(LDPC_FD_E_UNSUPPORTED, "no kernel variant with that many entries per lane for this code");
       c->tail_logr = value == 4 ? 2 : value == 8 ? 3 : 4;
       return LDPC_FD_OK;

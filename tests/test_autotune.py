@@ -20,7 +20,7 @@ def test_key_and_lane_choices():
     assert autotune.lane_choices(2, 4) == [4]
     assert autotune.lane_choices(3, 4) == [4, 8]
     assert autotune.lane_choices(6, 7) == [4, 8, 16]
-    assert autotune.lane_choices(8, 8) == [4, 8]
+    assert autotune.lane_choices(8, 8) == [4, 8, 16]
     assert autotune.lane_choices(8, 16) == [4, 8]
     assert autotune.lane_choices(2, 16) == [4]
 
