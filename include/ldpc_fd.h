@@ -352,17 +352,21 @@ int32_t ldpc_fd_pool_submit(ldpc_fd_pool pool, int32_t code, const float *llr, i
                             const uint64_t *tags, int32_t max_iter, int32_t *admitted);
 
 /* Enqueue `passes` (1..1000) passes over the active frames of every code: one
- * replay of a captured graph whose per-code branches run concurrently.  A code
- * whose admitted-but-unharvested frames number at most its tail threshold
- * (LDPC_FD_TUNE_TAIL_FRAMES) runs the few-frames form in this step, and a code
- * with none (every admitted frame harvested) is left out of the step; steps
- * are captured once per (passes, form per code) with the codes' tuning at that
- * time.  Asynchronous.  Errors: E_INVALID, E_UNSUPPORTED, E_HIP. */
+ * replay of a captured graph whose per-code branches run concurrently.  Each
+ * code's kernel forms follow a bound on its active frames: the smaller of its
+ * admitted-but-unharvested frames and its last active count read by
+ * ldpc_fd_pool_active plus the frames admitted since.  A code whose bound is
+ * at most its tail threshold (LDPC_FD_TUNE_TAIL_FRAMES) runs the few-frames
+ * form in this step (syndromes and retirement in one launch while the bound
+ * is at most 128), and a code whose bound is zero is left out of the step;
+ * steps are captured once per (passes, forms per code, schedule) with the
+ * codes' tuning at that time.  Asynchronous.  Errors: E_INVALID,
+ * E_UNSUPPORTED, E_HIP. */
 int32_t ldpc_fd_pool_step(ldpc_fd_pool pool, int32_t passes);
 
 /* How a step's per-code branches are ordered.  schedule 0 (default): every
  * code's passes run on its own stream, all concurrently.  schedule 1
- * (staggered): the code with the most work per pass (admitted-but-unharvested
+ * (staggered): the code with the most work per pass (its bound on active
  * frames times the bytes of one of its frame-rounds) starts once every other
  * code has run `lead` (0..1000) passes of the step; the rest overlaps.  With a
  * code that fills the GPU alone, concurrency only adds interference, while
@@ -377,7 +381,8 @@ int32_t ldpc_fd_pool_set_schedule(ldpc_fd_pool pool, int32_t schedule, int32_t l
 int32_t ldpc_fd_pool_harvest(ldpc_fd_pool pool, int32_t code, int32_t cap, uint64_t *tags, int32_t *iters,
                              uint32_t *status, uint8_t *hard, int32_t *n);
 
-/* Number of frames of code `code` still being decoded (synchronises). */
+/* Number of frames of code `code` still being decoded (synchronises); later
+ * steps choose the code's kernel forms from it (see ldpc_fd_pool_step). */
 int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
 
 /* Tuning of a code object's kernels (results are identical for every setting

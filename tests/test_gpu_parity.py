@@ -398,7 +398,10 @@ def test_edge_parallel_tail_pass_is_identical(case, precise):
     """Chunks with few active frames run the edge-parallel pass (one wavefront
     per edge); it sums a check's magnitudes in the same order as the
     check-serial pass, so decodes are bit-identical with it on and off (forced
-    here for every chunk by a large tail threshold)."""
+    here for every chunk by a large tail threshold), and with no tail form at
+    all (threshold 0: the full-batch pass and the two-launch syndromes and
+    retirement throughout, where the tail runs them as one launch once at most
+    128 frames are active)."""
     name, m, k, N, F, ebn0 = case
     print(f"[case] split tail {name} precise={precise} F={F}", flush=True)
     code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0)
@@ -413,9 +416,14 @@ def test_edge_parallel_tail_pass_is_identical(case, precise):
         for prec in precs:
             r = D.decode(gcode, L, 30, prec=prec, mode="fused")
             res[split, prec] = {k2: v.cpu().numpy() for k2, v in r.items()}
+    gcode.set_tuning(tail_frames=0)
+    for prec in precs:
+        r = D.decode(gcode, L, 30, prec=prec, mode="fused")
+        res["none", prec] = {k2: v.cpu().numpy() for k2, v in r.items()}
     for prec in precs:
         for key in ("hard", "synd", "iters", "status"):
             assert np.array_equal(res[0, prec][key], res[1, prec][key]), (prec, key)
+            assert np.array_equal(res["none", prec][key], res[1, prec][key]), (prec, key, "no tail")
     gcode.close()
 
 
