@@ -936,6 +936,7 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
     // frames of a workgroup are the same for all its wavefronts, so any_write
     // is uniform over the workgroup.
     constexpr int TQ = G::T * G::QP;
+    static_assert(KMAX >= 3, "the sums take stash rows 0..2");
     uint32_t* su = reinterpret_cast<uint32_t*>(stash);
     if (any_write) {
       for (int x = threadIdx.x; x < TQ; x += blockDim.x) {
