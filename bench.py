@@ -447,31 +447,38 @@ def main():
         # The same batch through the conventional log-domain SP decoder (the
         # comparison of Table 1): whole-decode time, and the time of its check
         # and variable kernels per frame-round next to the fused pass's.
-        ldec = D.Decoder(code, F, "fp32", "logsp")
-        ldec(llr, args.max_iter)
-        torch.cuda.synchronize()
-        D.profile_read(D.K_CHECK), D.profile_read(D.K_VAR)
-        D.profile_enable(not args.no_kernel_timing)
-        tl0 = time.perf_counter()
-        for _ in range(args.steps):
-            lout = ldec(llr, args.max_iter)
-        torch.cuda.synchronize()
-        lms = (time.perf_counter() - tl0) / args.steps * 1e3
-        D.profile_enable(False)
-        ck, _ = D.profile_read(D.K_CHECK)
-        vk, _ = D.profile_read(D.K_VAR)
-        lhard = lout["hard"].cpu().numpy()
-        lrounds = int(lout["iters"].sum())
-        logsp_line = {"ms_per_step": round(lms, 4),
-                      "value": round(F * batch.info_bits_per_frame / (lms / 1e3) / 1e6, 3),
-                      "fer": float(np.any(lhard != batch.cw, axis=1).mean()),
-                      "mean_iters": float(lout["iters"].float().mean()),
-                      "check_kernel_ms_per_step": round(ck / args.steps, 4),
-                      "var_kernel_ms_per_step": round(vk / args.steps, 4),
-                      "ns_per_frame_round": round((ck + vk) / args.steps * 1e6 / max(lrounds, 1), 2),
-                      "lfsp_ns_per_frame_round": round(kms / args.steps * 1e6 / max(int(out["iters"].sum()), 1), 2),
-                      "lfsp_speedup": round(lms / ms_step, 3)}
-        del ldec
+        def logsp_leg(prec):
+            ldec = D.Decoder(code, F, prec, "logsp")
+            ldec(llr, args.max_iter)
+            torch.cuda.synchronize()
+            D.profile_read(D.K_CHECK), D.profile_read(D.K_VAR)
+            D.profile_enable(not args.no_kernel_timing)
+            tl0 = time.perf_counter()
+            for _ in range(args.steps):
+                lout = ldec(llr, args.max_iter)
+            torch.cuda.synchronize()
+            lms = (time.perf_counter() - tl0) / args.steps * 1e3
+            D.profile_enable(False)
+            ck, _ = D.profile_read(D.K_CHECK)
+            vk, _ = D.profile_read(D.K_VAR)
+            lhard = lout["hard"].cpu().numpy()
+            lrounds = int(lout["iters"].sum())
+            del ldec
+            return {"ms_per_step": round(lms, 4),
+                    "value": round(F * batch.info_bits_per_frame / (lms / 1e3) / 1e6, 3),
+                    "fer": float(np.any(lhard != batch.cw, axis=1).mean()),
+                    "mean_iters": float(lout["iters"].float().mean()),
+                    "check_kernel_ms_per_step": round(ck / args.steps, 4),
+                    "var_kernel_ms_per_step": round(vk / args.steps, 4),
+                    "ns_per_frame_round": round((ck + vk) / args.steps * 1e6 / max(lrounds, 1), 2)}
+
+        logsp_line = logsp_leg("fp32")
+        logsp_line["lfsp_ns_per_frame_round"] = round(kms / args.steps * 1e6 / max(int(out["iters"].sum()), 1), 2)
+        logsp_line["lfsp_speedup"] = round(logsp_line["ms_per_step"] / ms_step, 3)
+        # The same decoder with one byte per message entry (log2 probabilities
+        # on the integer grid, the 8-bit message memory of the quantisation
+        # argument): a quarter of the message traffic.
+        logsp_line["log8"] = logsp_leg("log8")
 
     legs = None
     if args.mode == "fused" and default_form and not args.no_legs:

@@ -63,8 +63,12 @@ enum {
   LDPC_FD_E_HIP = -4          /* a HIP runtime call failed */
 };
 
-/* Storage type of the message state (arithmetic is FP32 in every case). */
-enum { LDPC_FD_FP32 = 0, LDPC_FD_FP16 = 1, LDPC_FD_BF16 = 2 };
+/* Storage type of the message state (arithmetic is FP32 in every case).
+ * LDPC_FD_LOG8 (LOGSP mode only): one byte per message entry, the code
+ * k = 0..255 of the log2 probability -k, rounded to nearest and saturating
+ * (the 8-bit form of the quantisation argument of Sec. 1 and Sec. 2.2; the
+ * same values as FP32 storage with QUANT_BITS = 8 and QUANT_STEP = 4096). */
+enum { LDPC_FD_FP32 = 0, LDPC_FD_FP16 = 1, LDPC_FD_BF16 = 2, LDPC_FD_LOG8 = 3 };
 
 /* Decoder variants (PLAIN and FUSED: identical results up to rounding order):
  *  PLAIN: one kernel per node type per round, flooding schedule of Sec. 2
@@ -86,7 +90,7 @@ enum { LDPC_FD_FP32 = 0, LDPC_FD_FP16 = 1, LDPC_FD_BF16 = 2 };
  *         log domain (forward/backward partial convolutions, 3(k-2) pairwise
  *         convolutions of q^2 log-sum-exp terms), the variable node adds log
  *         vectors; flooding schedule and stopping rule as PLAIN.  Same outputs
- *         as the Log-Fourier modes up to rounding; FP32 storage only; the
+ *         as the Log-Fourier modes up to rounding; FP32 or LOG8 storage; the
  *         PRECISE and DECISION_MFMA tuning keys do not apply.
  *  FSP:   the linear-domain Fourier SP of Sec. 3.1 (the algorithm the
  *         Log-Fourier SP is derived from): messages are P(z) itself (FP32,

@@ -185,8 +185,12 @@ bool logsp_check(const NodeArgs& a, hipStream_t s) {
   const long items = (long)a.nf * a.cd.M;
   if (items == 0) return true;
   const size_t lds = (size_t)(3 * a.kmax + 1) * (1 << LOGQ) * sizeof(float);
-  hipLaunchKernelGGL(k_logsp_check<LOGQ>, dim3(ls_grid(items)), dim3(64), lds, s, a.cd, a.nf, a.alist, a.kmax, a.in,
-                     a.out);
+  if (a.log8)
+    hipLaunchKernelGGL((k_logsp_check<LOGQ, uint8_t>), dim3(ls_grid(items)), dim3(64), lds, s, a.cd, a.nf, a.alist,
+                       a.kmax, (const uint8_t*)a.in, (uint8_t*)a.out);
+  else
+    hipLaunchKernelGGL((k_logsp_check<LOGQ, float>), dim3(ls_grid(items)), dim3(64), lds, s, a.cd, a.nf, a.alist,
+                       a.kmax, a.in, a.out);
   return true;
 }
 
@@ -195,8 +199,12 @@ bool logsp_var(const NodeArgs& a, hipStream_t s) {
   const long items = (long)a.nf * a.cd.N;
   if (items == 0) return true;
   const size_t lds = (size_t)a.jmax * (1 << LOGQ) * sizeof(float);
-  hipLaunchKernelGGL(k_logsp_var<LOGQ>, dim3(ls_grid(items)), dim3(64), lds, s, a.cd, a.nf, a.alist, a.llr, a.in,
-                     a.out, a.hard, a.fsw, a.first);
+  if (a.log8)
+    hipLaunchKernelGGL((k_logsp_var<LOGQ, uint8_t>), dim3(ls_grid(items)), dim3(64), lds, s, a.cd, a.nf, a.alist,
+                       a.llr, (const uint8_t*)a.in, (uint8_t*)a.out, a.hard, a.fsw, a.first);
+  else
+    hipLaunchKernelGGL((k_logsp_var<LOGQ, float>), dim3(ls_grid(items)), dim3(64), lds, s, a.cd, a.nf, a.alist,
+                       a.llr, a.in, a.out, a.hard, a.fsw, a.first);
   return true;
 }
 

@@ -62,6 +62,7 @@ struct NodeArgs {
   uint8_t* fsw;
   int first;
   bool lin;             // linear Fourier SP variable node (k_var_gen)
+  bool log8 = false;    // LOGSP: in/out hold 8-bit log2-probability codes (LDPC_FD_LOG8)
 };
 
 // Each returns false when no kernel variant exists for (kmax, logr).

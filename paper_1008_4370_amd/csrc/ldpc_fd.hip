@@ -171,8 +171,9 @@ struct FusedWs {
   int* rnd;  // [F] per-frame round
 };
 
-size_t plain_layout(const ldpc_fd_code_s* c, int F, char* base, PlainWs* w) {
-  const size_t msg = align256((size_t)F * c->E * c->q * 4);
+// esize: bytes per message entry (4; 1 for the LOGSP decoder's 8-bit codes).
+size_t plain_layout(const ldpc_fd_code_s* c, int F, char* base, PlainWs* w, int esize = 4) {
+  const size_t msg = align256((size_t)F * c->E * c->q * esize);
   size_t off = 0;
   auto take = [&](size_t n) { char* p = base ? base + off : nullptr; off += align256(n); return p; };
   char* p0 = take(msg);
@@ -471,11 +472,13 @@ int32_t ldpc_fd_code_info(ldpc_fd_code c, int32_t* M, int32_t* N, int32_t* m, in
 
 int32_t ldpc_fd_workspace_bytes(ldpc_fd_code c, int32_t frames, int32_t prec, int32_t mode, int64_t* bytes) {
   if (!c || !bytes || frames < 0) return fail(LDPC_FD_E_INVALID, "bad argument");
-  if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
+  if (prec < 0 || prec > 3) return fail(LDPC_FD_E_INVALID, "unknown precision");
+  if (prec == LDPC_FD_LOG8 && mode != LDPC_FD_MODE_LOGSP)
+    return fail(LDPC_FD_E_UNSUPPORTED, "8-bit log2-probability storage is for the LOGSP decoder");
   if (mode == LDPC_FD_MODE_PLAIN || mode == LDPC_FD_MODE_LOGSP || mode == LDPC_FD_MODE_FSP) {
-    if (prec != LDPC_FD_FP32)
-      return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN, LOGSP and FSP decoders store FP32 messages only");
-    *bytes = (int64_t)plain_layout(c, frames, nullptr, nullptr);
+    if (prec != LDPC_FD_FP32 && prec != LDPC_FD_LOG8)
+      return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN, LOGSP and FSP decoders store FP32 messages (LOGSP also LOG8)");
+    *bytes = (int64_t)plain_layout(c, frames, nullptr, nullptr, prec == LDPC_FD_LOG8 ? 1 : 4);
   } else if (mode == LDPC_FD_MODE_FUSED) {
     *bytes = (int64_t)fused_layout(c, frames, prec, nullptr, nullptr);
   } else {
@@ -519,21 +522,33 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     // F frames in order; each retirement appends the continuing frames to
     // w.alist (in any order: frames are independent) and the host reads their
     // count, which sizes the next round's launches.
+    // LOG8: the message arrays hold one byte per entry (the emulated
+    // QUANT_BITS grid does not apply)
+    const bool log8 = prec == LDPC_FD_LOG8;
     PlainWs w;
-    plain_layout(c, F, (char*)workspace, &w);
+    plain_layout(c, F, (char*)workspace, &w, log8 ? 1 : 4);
     hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, w.active, w.unsat, w.mism, (int*)nullptr,
                        (int*)nullptr, iters, status, (int*)nullptr, 0);
+    auto args = [&](int nf, const int* list, const float* l, const float* in, float* out, uint8_t* hd, uint8_t* fw,
+                    int first) {
+      NodeArgs a = node_args(c, nf, list, l, in, out, hd, fw, first);
+      a.log8 = log8;
+      return a;
+    };
+    auto quant = [&](float* msg) {
+      if (!log8) launch_quantise(c, F, msg, 2, s);
+    };
     bool ok = true;
-    timed(LDPC_FD_K_VAR, s, [&] { ok = run_logsp_var(c, node_args(c, F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1), s); });
+    timed(LDPC_FD_K_VAR, s, [&] { ok = run_logsp_var(c, args(F, nullptr, llr, nullptr, w.v2c, hard, w.fsw, 1), s); });
     if (!ok) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
-    launch_quantise(c, F, w.v2c, 2, s);
+    quant(w.v2c);
     int nf = F;
     const int* list = nullptr;
     for (int ell = 1; ell <= max_iter; ++ell) {
-      timed(LDPC_FD_K_CHECK, s, [&] { run_logsp_check(c, node_args(c, nf, list, nullptr, w.v2c, w.c2v, nullptr, nullptr, 0), s); });
-      launch_quantise(c, F, w.c2v, 2, s);
-      timed(LDPC_FD_K_VAR, s, [&] { run_logsp_var(c, node_args(c, nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0), s); });
-      launch_quantise(c, F, w.v2c, 2, s);
+      timed(LDPC_FD_K_CHECK, s, [&] { run_logsp_check(c, args(nf, list, nullptr, w.v2c, w.c2v, nullptr, nullptr, 0), s); });
+      quant(w.c2v);
+      timed(LDPC_FD_K_VAR, s, [&] { run_logsp_var(c, args(nf, list, llr, w.c2v, w.v2c, hard, w.fsw, 0), s); });
+      quant(w.v2c);
       launch_syndrome(c, F, hard, w.fsw, synd, nullptr, w.unsat, w.mism, nullptr, nullptr, w.active, s);
       HIP_TRY(hipMemsetAsync(w.count, 0, 4, s));
       hipLaunchKernelGGL(k_retire_plain, dim3(fb), dim3(256), 0, s, F, ell, max_iter, w.active, w.unsat, w.mism,

@@ -15,6 +15,16 @@ namespace ldpcfd {
 
 constexpr float kLsFloor = 200.0f;
 
+// Message words of the Log-SP decoder: FP32 log2 probabilities, or 8-bit
+// codes k of the log2 probability -k (rounded to nearest, saturating at 255;
+// every stored value lies in [-kLsFloor, 0]).
+__device__ __forceinline__ float ls_load(const float* p, size_t i) { return p[i]; }
+__device__ __forceinline__ float ls_load(const uint8_t* p, size_t i) { return -(float)p[i]; }
+__device__ __forceinline__ void ls_store(float* p, size_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void ls_store(uint8_t* p, size_t i, float v) {
+  p[i] = (uint8_t)__builtin_fminf(__builtin_rintf(-v), 255.0f);
+}
+
 template <int LOGQ>
 struct LsGeo {
   static constexpr int Q = 1 << LOGQ;
@@ -89,9 +99,9 @@ __device__ __forceinline__ void ls_conv(const float* f, const float* g, float* o
 // back to log2 (less its maximum, floored).  LDS per wavefront (3 kmax + 1) Q
 // floats: the label-mapped inputs, the forward and the backward partials, kmax
 // rows each, and one output row.
-template <int LOGQ>
+template <int LOGQ, typename M>
 __global__ __launch_bounds__(64) void k_logsp_check(DevCode cd, int nf, const int* __restrict__ alist, int kmax,
-                                                    const float* __restrict__ v2c, float* __restrict__ c2v) {
+                                                    const M* __restrict__ v2c, M* __restrict__ c2v) {
   using G = LsGeo<LOGQ>;
   extern __shared__ float ls[];
   float* in = ls;                       // [kmax][Q]
@@ -109,11 +119,11 @@ __global__ __launch_bounds__(64) void k_logsp_check(DevCode cd, int nf, const in
     for (int j = 0; j < deg; ++j) {
       const int e = e0 + j;
       const int hinv = cd.ginv[cd.e_label[e]];
-      const float* src = v2c + ((size_t)f * cd.E + e) * G::Q;
+      const M* src = v2c + ((size_t)f * cd.E + e) * G::Q;
 #pragma unroll
       for (int xj = 0; xj < G::X; ++xj) {
         const int x = lane + 64 * xj;
-        if (x < G::Q) in[j * G::Q + x] = __builtin_amdgcn_exp2f(src[gf_mul(cd, hinv, x)]);
+        if (x < G::Q) in[j * G::Q + x] = __builtin_amdgcn_exp2f(ls_load(src, gf_mul(cd, hinv, x)));
       }
     }
     __syncthreads();
@@ -159,11 +169,11 @@ __global__ __launch_bounds__(64) void k_logsp_check(DevCode cd, int nf, const in
         mx = __builtin_fmaxf(mx, v[xj]);
       }
       const float lmx = __builtin_amdgcn_logf(wave_max(mx));
-      float* dst = c2v + ((size_t)f * cd.E + e) * G::Q;
+      M* dst = c2v + ((size_t)f * cd.E + e) * G::Q;
 #pragma unroll
       for (int xj = 0; xj < G::X; ++xj) {
         const int x = lane + 64 * xj;
-        if (x < G::Q) dst[x] = __builtin_fmaxf(__builtin_amdgcn_logf(v[xj]) - lmx, -kLsFloor);
+        if (x < G::Q) ls_store(dst, x, __builtin_fmaxf(__builtin_amdgcn_logf(v[xj]) - lmx, -kLsFloor));
       }
       __syncthreads();
     }
@@ -310,16 +320,16 @@ __device__ __forceinline__ void decide_wave2(const float (&lp)[LsGeo<LOGQ>::X], 
 
 // The Log-SP variable node of a weight-2 column, in registers: the message to
 // each check is the prior plus the other check's message.
-template <int LOGQ>
+template <int LOGQ, typename M>
 __device__ __forceinline__ void logsp_var_w2(const DevCode& cd, int f, int v, int e1, int e2,
-                                             const float (&lp)[LsGeo<LOGQ>::X], const float* __restrict__ c2v,
-                                             float* __restrict__ v2c, uint8_t* __restrict__ hard,
+                                             const float (&lp)[LsGeo<LOGQ>::X], const M* __restrict__ c2v,
+                                             M* __restrict__ v2c, uint8_t* __restrict__ hard,
                                              uint8_t* __restrict__ fsw, int first) {
   using G = LsGeo<LOGQ>;
   const int lane = lane_id();
   const uint64_t c1 = cd.colsT[cd.e_label[e1]], c2 = cd.colsT[cd.e_label[e2]];
-  const float* m1 = c2v + ((size_t)f * cd.E + e1) * G::Q;
-  const float* m2 = c2v + ((size_t)f * cd.E + e2) * G::Q;
+  const M* m1 = c2v + ((size_t)f * cd.E + e1) * G::Q;
+  const M* m2 = c2v + ((size_t)f * cd.E + e2) * G::Q;
   float a1[G::X], a2[G::X], r1[G::X];
 #pragma unroll
   for (int xj = 0; xj < G::X; ++xj) {
@@ -327,8 +337,8 @@ __device__ __forceinline__ void logsp_var_w2(const DevCode& cd, int f, int v, in
     a1[xj] = a2[xj] = lp[xj];
     r1[xj] = 0.0f;
     if (!first && x < G::Q) {
-      r1[xj] = m1[x];
-      a1[xj] += m2[x];  // to the check of e1: the prior and the message from the check of e2
+      r1[xj] = ls_load(m1, x);
+      a1[xj] += ls_load(m2, x);  // to the check of e1: the prior and the message from the check of e2
       a2[xj] += r1[xj];
     }
   }
@@ -337,8 +347,8 @@ __device__ __forceinline__ void logsp_var_w2(const DevCode& cd, int f, int v, in
   for (int xj = 0; xj < G::X; ++xj) {
     const int x = lane + 64 * xj;
     if (x < G::Q) {
-      v2c[((size_t)f * cd.E + e1) * G::Q + x] = __builtin_fmaxf(a1[xj] - mx1, -kLsFloor);
-      v2c[((size_t)f * cd.E + e2) * G::Q + x] = __builtin_fmaxf(a2[xj] - mx2, -kLsFloor);
+      ls_store(v2c, ((size_t)f * cd.E + e1) * G::Q + x, __builtin_fmaxf(a1[xj] - mx1, -kLsFloor));
+      ls_store(v2c, ((size_t)f * cd.E + e2) * G::Q + x, __builtin_fmaxf(a2[xj] - mx2, -kLsFloor));
     }
   }
   if (first) return;
@@ -361,10 +371,10 @@ __device__ __forceinline__ void logsp_var_w2(const DevCode& cd, int f, int v, in
 // from the other checks of v (log domain: a sum), maximum 0, floored, and the
 // posterior (prior plus all messages) gives the decision.  LDS per wavefront:
 // the j incoming rows (jmax rows of Q floats).
-template <int LOGQ>
+template <int LOGQ, typename M>
 __global__ __launch_bounds__(64) void k_logsp_var(DevCode cd, int nf, const int* __restrict__ alist,
-                                                  const float* __restrict__ llr, const float* __restrict__ c2v,
-                                                  float* __restrict__ v2c, uint8_t* __restrict__ hard,
+                                                  const float* __restrict__ llr, const M* __restrict__ c2v,
+                                                  M* __restrict__ v2c, uint8_t* __restrict__ hard,
                                                   uint8_t* __restrict__ fsw, int first) {
   using G = LsGeo<LOGQ>;
   extern __shared__ float rows[];  // [jmax][Q]
@@ -377,27 +387,27 @@ __global__ __launch_bounds__(64) void k_logsp_var(DevCode cd, int nf, const int*
     float lp[G::X];
     log_prior<LOGQ>(llr + ((size_t)f * cd.N + v) * LOGQ, lp);
     if (ee - eb == 2) {  // the (2,k) codes: registers only
-      logsp_var_w2<LOGQ>(cd, f, v, cd.v_list[eb], cd.v_list[eb + 1], lp, c2v, v2c, hard, fsw, first);
+      logsp_var_w2<LOGQ, M>(cd, f, v, cd.v_list[eb], cd.v_list[eb + 1], lp, c2v, v2c, hard, fsw, first);
       continue;
     }
     if (first) {
       const float mx = row_max<LOGQ>(lp);
       for (int k = eb; k < ee; ++k) {
-        float* dst = v2c + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
+        M* dst = v2c + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
 #pragma unroll
         for (int xj = 0; xj < G::X; ++xj) {
           const int x = lane + 64 * xj;
-          if (x < G::Q) dst[x] = __builtin_fmaxf(lp[xj] - mx, -kLsFloor);
+          if (x < G::Q) ls_store(dst, x, __builtin_fmaxf(lp[xj] - mx, -kLsFloor));
         }
       }
       continue;
     }
     for (int k = eb; k < ee; ++k) {
-      const float* src = c2v + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
+      const M* src = c2v + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
 #pragma unroll
       for (int xj = 0; xj < G::X; ++xj) {
         const int x = lane + 64 * xj;
-        if (x < G::Q) rows[(k - eb) * G::Q + x] = src[x];
+        if (x < G::Q) rows[(k - eb) * G::Q + x] = ls_load(src, x);
       }
     }
     __syncthreads();
@@ -412,11 +422,11 @@ __global__ __launch_bounds__(64) void k_logsp_var(DevCode cd, int nf, const int*
             if (s != k) a[xj] += rows[(s - eb) * G::Q + x];
       }
       const float mx = row_max<LOGQ>(a);
-      float* dst = v2c + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
+      M* dst = v2c + ((size_t)f * cd.E + cd.v_list[k]) * G::Q;
 #pragma unroll
       for (int xj = 0; xj < G::X; ++xj) {
         const int x = lane + 64 * xj;
-        if (x < G::Q) dst[x] = __builtin_fmaxf(a[xj] - mx, -kLsFloor);
+        if (x < G::Q) ls_store(dst, x, __builtin_fmaxf(a[xj] - mx, -kLsFloor));
       }
     }
     float post[G::X];

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libldpcfd.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "ldpc_fd.h")
 
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP = 0, -1, -2, -3, -4
-PREC = {"fp32": 0, "fp16": 1, "bf16": 2}
+PREC = {"fp32": 0, "fp16": 1, "bf16": 2, "log8": 3}
 MODE = {"plain": 0, "fused": 1, "logsp": 2, "fsp": 3}
 STATUS_CONVERGED, STATUS_MISMATCH = 1, 2
 K_FUSED, K_CHECK, K_VAR = 0, 1, 2

@@ -130,3 +130,51 @@ def test_logsp_edge_cases():
         D.workspace_bytes(gcode, 5, "fp16", "logsp")
     assert ei.value.rc == D.E_UNSUPPORTED
     gcode.close()
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[5], CASES[7], CASES[8]], ids=lambda c: c[0])
+def test_logsp_8bit_storage_equals_the_emulated_8bit_grid(case):
+    """LDPC_FD_LOG8: messages stored as one byte (code k of the log2
+    probability -k).  The decode is identical, frame by frame, to FP32
+    storage with every stored message rounded onto the same grid in place
+    (QUANT_BITS = 8, QUANT_STEP = 4096: step 1), and the workspace holds a
+    quarter of the message bytes."""
+    name, m, k, N, F, ebn0 = case
+    print(f"[case] logsp 8-bit {name} F={F}", flush=True)
+    code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0)
+    gcode = D.Code.from_synth(code)
+    L = _dev(llr)
+    r8 = {k2: v.cpu().numpy() for k2, v in D.decode(gcode, L, 30, prec="log8", mode="logsp").items()}
+    gcode.set_tuning(quant_bits=8, quant_step=4096)
+    rq = {k2: v.cpu().numpy() for k2, v in D.decode(gcode, L, 30, prec="fp32", mode="logsp").items()}
+    gcode.set_tuning(quant_bits=0)
+    for key in ("hard", "synd", "iters", "status"):
+        assert np.array_equal(r8[key], rq[key]), key
+    _check_outputs(r8, enc, 30)
+    w8 = D.workspace_bytes(gcode, F, "log8", "logsp")
+    w32 = D.workspace_bytes(gcode, F, "fp32", "logsp")
+    msg = F * code.E * code.q
+    assert w32 - w8 >= 2 * (3 * msg) - 2 * 512, (w32, w8)
+    gcode.close()
+
+
+def test_logsp_8bit_storage_gf64_n1000_fer():
+    """GF(64) (2,6) N=1000, 2048 frames at 2.5 dB: 8-bit Log-SP messages keep
+    the FP32 Log-SP frame error rate (the log domain holds its FER down to
+    5-bit messages), and LOG8 is rejected outside the LOGSP mode."""
+    b = synth.make_batch("gf64_n1000", point=2, frames=2048)
+    print("[case] gf64_n1000 logsp 8-bit 2048 frames", flush=True)
+    o32 = _full_run(b.code, b.llr, 100, "fp32", "logsp")
+    o8 = _full_run(b.code, b.llr, 100, "log8", "logsp")
+    c8 = _check_outputs(o8, b.enc, 100)
+    fer32 = np.any(o32["hard"] != b.cw, axis=1).mean()
+    fer8 = np.any(o8["hard"] != b.cw, axis=1).mean()
+    print(f"[logsp 8-bit] FER fp32 {fer32:.2e} log8 {fer8:.2e}", flush=True)
+    assert fer8 <= fer32 + 3.0 / 2048
+    assert c8.mean() > 0.99
+    gcode = D.Code.from_synth(b.code)
+    for mode in ("fused", "plain", "fsp"):
+        with pytest.raises(D.LdpcFdError) as ei:
+            D.workspace_bytes(gcode, 16, "log8", mode)
+        assert ei.value.rc == D.E_UNSUPPORTED
+    gcode.close()
