@@ -341,6 +341,13 @@ int32_t ldpc_fd_pool_create(const ldpc_fd_code *codes, int32_t ncodes, const int
 int32_t ldpc_fd_pool_create_budget(const ldpc_fd_code *codes, int32_t ncodes, int64_t hbm_budget, int32_t prec,
                                    void *stream, ldpc_fd_pool *out);
 
+/* The slot counts ldpc_fd_pool_create_budget gives for these arguments, into
+ * slots[0..ncodes) (host memory), without allocating (for sizing work to a
+ * pool before creating it).  Errors: E_INVALID; E_NOMEM when a code's share
+ * holds no slot. */
+int32_t ldpc_fd_pool_budget_slots(const ldpc_fd_code *codes, int32_t ncodes, int64_t hbm_budget, int32_t prec,
+                                  int32_t *slots);
+
 /* Synchronise the pool's stream and free all its resources (NULL: no-op). */
 int32_t ldpc_fd_pool_destroy(ldpc_fd_pool pool);
 

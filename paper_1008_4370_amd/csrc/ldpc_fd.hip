@@ -1127,14 +1127,12 @@ int32_t ldpc_fd_run_rounds(ldpc_fd_code c, int32_t F, const float* llr, int32_t 
   return LDPC_FD_OK;
 }
 
-int32_t ldpc_fd_pool_create_budget(const ldpc_fd_code* codes, int32_t ncodes, int64_t hbm_budget, int32_t prec,
-                                   void* stream, ldpc_fd_pool* out) {
-  if (!out) return fail(LDPC_FD_E_INVALID, "out is NULL");
-  *out = nullptr;
+int32_t ldpc_fd_pool_budget_slots(const ldpc_fd_code* codes, int32_t ncodes, int64_t hbm_budget, int32_t prec,
+                                  int32_t* slots) {
   if (!codes || ncodes < 1 || ncodes > 16) return fail(LDPC_FD_E_INVALID, "1..16 codes required");
+  if (!slots) return fail(LDPC_FD_E_INVALID, "slots is NULL");
   if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
   if (hbm_budget < 1) return fail(LDPC_FD_E_INVALID, "budget must be positive");
-  std::vector<int32_t> slots(ncodes);
   const int64_t share = hbm_budget / ncodes;
   for (int k = 0; k < ncodes; ++k) {
     if (!codes[k]) return fail(LDPC_FD_E_INVALID, "NULL code");
@@ -1145,6 +1143,16 @@ int32_t ldpc_fd_pool_create_budget(const ldpc_fd_code* codes, int32_t ncodes, in
                                        std::to_string(per) + " bytes each)");
     slots[k] = (int32_t)std::min<int64_t>(n, 1 << 22);
   }
+  return LDPC_FD_OK;
+}
+
+int32_t ldpc_fd_pool_create_budget(const ldpc_fd_code* codes, int32_t ncodes, int64_t hbm_budget, int32_t prec,
+                                   void* stream, ldpc_fd_pool* out) {
+  if (!out) return fail(LDPC_FD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::vector<int32_t> slots(std::max(ncodes, 1));
+  const int32_t rc = ldpc_fd_pool_budget_slots(codes, ncodes, hbm_budget, prec, slots.data());
+  if (rc) return rc;
   return ldpc_fd_pool_create(codes, ncodes, slots.data(), prec, stream, out);
 }
 

@@ -62,6 +62,7 @@ _SIGS = {
     "ldpc_fd_pool_active": (_i32, [_c_void_p, _i32, ctypes.POINTER(_i32)]),
     "ldpc_fd_pool_create_budget": (_i32, [ctypes.POINTER(_c_void_p), _i32, _i64, _i32, _c_void_p,
                                           ctypes.POINTER(_c_void_p)]),
+    "ldpc_fd_pool_budget_slots": (_i32, [ctypes.POINTER(_c_void_p), _i32, _i64, _i32, ctypes.POINTER(_i32)]),
     "ldpc_fd_decode_ex": (_i32, [_c_void_p, _c_void_p, _c_void_p]),
     "ldpc_fd_pool_set_schedule": (_i32, [_c_void_p, _i32, _i32]),
     "ldpc_fd_run_rounds": (_i32, [_c_void_p, _i32, _c_void_p, _i32, _i32, _c_void_p, _c_void_p, _c_void_p,
@@ -339,6 +340,15 @@ def pool_slot_bytes(code: Code, prec: str = "fp32") -> int:
     out = _i64()
     _check(lib().ldpc_fd_pool_slot_bytes(code.handle, PREC[prec], ctypes.byref(out)))
     return out.value
+
+
+def pool_budget_slots(codes, hbm_budget: int, prec: str = "fp32") -> list[int]:
+    """Slot counts a pool created from an HBM budget of `hbm_budget` bytes gets
+    (ldpc_fd_pool_budget_slots)."""
+    arr = (ctypes.c_void_p * len(codes))(*[c.handle for c in codes])
+    out = (_i32 * len(codes))()
+    _check(lib().ldpc_fd_pool_budget_slots(arr, len(codes), int(hbm_budget), PREC[prec], out))
+    return [int(x) for x in out]
 
 
 class Pool:

@@ -3,8 +3,8 @@
 Requests arrive as a Poisson process in wall-clock time; each request carries
 `request_frames` frames of one code (chosen uniformly) at one Eb/N0 (uniform
 over the given range).  Requests are admitted FIFO per code into free frame
-slots, whose number per code follows from an HBM budget divided by the
-per-slot footprint (ldpc_fd_pool_slot_bytes).  Between admissions the pool
+slots, whose number per code follows from an HBM budget: an equal share per
+code and the most slots whose device bytes fit it (ldpc_fd_pool_budget_slots).  Between admissions the pool
 runs a chunk of passes over every active frame of every code; stopped frames
 are harvested and their slots freed at once, so new requests join frames in
 flight.  Reported: per-frame and per-request latency (arrival to harvest)
@@ -65,9 +65,9 @@ def bank_from_batch(batch, gcode=None, device="cuda"):
 
 
 def slots_for_budget(banks, hbm_budget: int, prec: str):
-    """Equal share of the budget per code, divided by the per-slot footprint."""
-    share = hbm_budget // len(banks)
-    return [max(1, share // D.pool_slot_bytes(b.gcode, prec)) for b in banks]
+    """The slot counts of a pool sized from the budget: an equal share per
+    code, the most slots whose device bytes fit it."""
+    return D.pool_budget_slots([b.gcode for b in banks], hbm_budget, prec)
 
 
 def serve(banks, offered_fps: float, duration_s: float, prec: str = "fp16", max_iter: int = 100,

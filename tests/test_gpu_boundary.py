@@ -127,6 +127,7 @@ def test_pool_sized_from_a_budget():
     pool = D.Pool(codes, None, "fp16", hbm_budget=budget)
     for k, c in enumerate(codes):
         assert pool.slots[k] == (budget // 2) // D.pool_slot_bytes(c, "fp16")
+    assert pool.slots == D.pool_budget_slots(codes, budget, "fp16")
     pool.close()
     with pytest.raises(D.LdpcFdError) as ei:
         D.Pool(codes, None, "fp32", hbm_budget=1000)
