@@ -197,7 +197,8 @@ int32_t ldpc_fd_decode_prior(ldpc_fd_code code, int32_t frames, const float *pri
  *   P(0) = 1, so the difference to an FP32 round is the one-round storage
  *   error (PLAIN: FP32 only).  The call allocates temporary device memory and
  *   synchronises.
- * Errors: E_INVALID, E_UNSUPPORTED (PLAIN or LOGSP with prec != FP32), E_HIP. */
+ * Errors: E_INVALID, E_UNSUPPORTED (PLAIN or LOGSP with prec != FP32; LDPC_FD_LOG8,
+ * which whole LOGSP decodes take), E_HIP. */
 int32_t ldpc_fd_round(ldpc_fd_code code, int32_t frames, const float *llr, const float *c2v_in,
                       float *v2c_out, float *c2v_out, uint8_t *hard, uint8_t *fsynd,
                       uint8_t *synd, int32_t mode, int32_t prec, void *stream);
@@ -293,7 +294,9 @@ int32_t ldpc_fd_posterior(ldpc_fd_code code, int32_t frames, const float *llr, c
  * round it stopped at (iters[f], the decode's device output), read from the
  * message buffer that holds that round's check-to-variable messages.
  * Errors: E_INVALID (NULL arguments with frames > 0, unknown prec, workspace
- *   smaller than the fused decode's), E_HIP. */
+ *   smaller than the fused decode's), E_UNSUPPORTED (a code with column weights
+ *   other than 2, or LDPC_FD_LOG8, neither of which a FUSED decode takes),
+ *   E_HIP. */
 int32_t ldpc_fd_decode_posterior(ldpc_fd_code code, int32_t frames, const float *llr, int32_t prec,
                                  const int32_t *iters, const void *workspace, int64_t workspace_bytes,
                                  double *posterior, void *stream);
@@ -445,7 +448,8 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *     k = 0 .. 2^(b-1) - 1 (nearest, saturating).  FSP (linear P in [-1, 1]):
  *     b-bit two's complement fixed point with step 2^-(b-1).  LOGSP (log2
  *     pmfs <= 0): b-bit unsigned -k * step, k = 0 .. 2^b - 1.  FUSED ignores
- *     it.  Changes results by design.
+ *     it, and so does LOGSP with LDPC_FD_LOG8 storage (already 8-bit).
+ *     Changes results by design.
  *   LDPC_FD_TUNE_QUANT_STEP: the PLAIN and LOGSP step in units of 2^-12
  *     (1..65536; default 256, i.e. 1/16).
  * Errors: E_INVALID (unknown key or value), E_UNSUPPORTED (no such variant). */

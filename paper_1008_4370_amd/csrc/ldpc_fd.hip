@@ -788,6 +788,7 @@ int32_t round_check(ldpc_fd_code c, int32_t F, const float* llr, const float* c2
   if (mode == LDPC_FD_MODE_FUSED && c->precise != 2 && prec != LDPC_FD_FP32)
     return fail(LDPC_FD_E_UNSUPPORTED, kPmfOnlyDefault);
   if (mode < LDPC_FD_MODE_PLAIN || mode > LDPC_FD_MODE_FSP) return fail(LDPC_FD_E_INVALID, "unknown mode");
+  if (prec == LDPC_FD_LOG8) return fail(LDPC_FD_E_UNSUPPORTED, "8-bit storage is for whole LOGSP decodes only");
   if (prec < 0 || prec > 2) return fail(LDPC_FD_E_INVALID, "unknown precision");
   if (mode != LDPC_FD_MODE_FUSED && prec != LDPC_FD_FP32)
     return fail(LDPC_FD_E_UNSUPPORTED, "PLAIN, LOGSP and FSP are FP32 only");

@@ -177,4 +177,8 @@ def test_logsp_8bit_storage_gf64_n1000_fer():
         with pytest.raises(D.LdpcFdError) as ei:
             D.workspace_bytes(gcode, 16, "log8", mode)
         assert ei.value.rc == D.E_UNSUPPORTED
+    # one round from an imported state is an FP32 operation
+    with pytest.raises(D.LdpcFdError) as ei:
+        D.round_step(gcode, _dev(b.llr[:4]), None, "logsp", "log8")
+    assert ei.value.rc == D.E_UNSUPPORTED
     gcode.close()
