@@ -452,11 +452,15 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *     Changes results by design.
  *   LDPC_FD_TUNE_QUANT_STEP: the PLAIN and LOGSP step in units of 2^-12
  *     (1..65536; default 256, i.e. 1/16).
+ *   LDPC_FD_TUNE_TAIL_CHUNK: FUSED passes per captured graph (host read of the
+ *     active count between graphs) for chunks that start with at most
+ *     TAIL_FRAMES active frames; 0 (default) = CHUNK; 1..1000.  Results are
+ *     identical for every value.
  * Errors: E_INVALID (unknown key or value), E_UNSUPPORTED (no such variant). */
 enum { LDPC_FD_TUNE_LANE_ENTRIES = 0, LDPC_FD_TUNE_GRID_BLOCKS = 1, LDPC_FD_TUNE_CHUNK = 2,
        LDPC_FD_TUNE_GRAPHS = 3, LDPC_FD_TUNE_TAIL_ENTRIES = 4, LDPC_FD_TUNE_TAIL_FRAMES = 5,
        LDPC_FD_TUNE_PRECISE = 6, LDPC_FD_TUNE_DECISION_MFMA = 7, LDPC_FD_TUNE_TAIL_SPLIT = 8,
-       LDPC_FD_TUNE_QUANT_BITS = 9, LDPC_FD_TUNE_QUANT_STEP = 10 };
+       LDPC_FD_TUNE_QUANT_BITS = 9, LDPC_FD_TUNE_QUANT_STEP = 10, LDPC_FD_TUNE_TAIL_CHUNK = 11 };
 int32_t ldpc_fd_set_tuning(ldpc_fd_code code, int32_t key, int32_t value);
 int32_t ldpc_fd_get_tuning(ldpc_fd_code code, int32_t key, int32_t *value);
 

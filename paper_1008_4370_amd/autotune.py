@@ -61,6 +61,7 @@ def apply(code: D.Code, prec: str, frames: int, path: str = TABLE) -> dict | Non
                     graphs=1)
     if "tail_entries" in ent:
         code.set_tuning(tail_entries=ent["tail_entries"], tail_frames=ent["tail_frames"])
+    code.set_tuning(tail_chunk=ent.get("tail_chunk", 0))
     return ent
 
 
@@ -79,10 +80,11 @@ def _time_decode(dec, llr, max_iter, reps):
 
 def tune(code: D.Code, llr, prec: str = "fp32", max_iter: int = 100, reps: int = 3,
          grid_blocks=(2048, 4096, 8192, 16384, 32768), chunks=(4, 8), tail_frames=(0, 32, 128, 512, 2048, 1 << 20),
-         path: str | None = TABLE, log=None) -> dict:
+         tail_chunks=(0, 16, 32), path: str | None = TABLE, log=None) -> dict:
     """Sweep the launch choices for decoding `llr` (device [F][N][m]) and record
     the best: first the main variant, grid and chunk (tail variant at its
-    defaults), then the tail variant and its threshold."""
+    defaults), then the tail variant and its threshold, then the number of
+    passes per captured graph in the tail."""
     m, kmax, N = code.m, code.kmax, code.N
     F = int(llr.shape[0])
     dec = D.Decoder(code, F, prec, "fused")
@@ -105,12 +107,19 @@ def tune(code: D.Code, llr, prec: str = "fp32", max_iter: int = 100, reps: int =
     for te, tf in itertools.product(lane_choices(m, kmax), tail_frames):
         tail.append((run(lane_entries=le, grid_blocks=gb, chunk=ch, tail_entries=te, tail_frames=tf), te, tf))
     t, te, tf = min(tail)
+    tcs = [(t, 0)]
+    for tc in tail_chunks:
+        if tc:
+            tcs.append((run(lane_entries=le, grid_blocks=gb, chunk=ch, tail_entries=te, tail_frames=tf,
+                            tail_chunk=tc), tc))
+    t, tc = min(tcs)
     ent = {"lane_entries": le, "grid_blocks": gb, "chunk": ch, "tail_entries": te, "tail_frames": tf,
-           "ms": round(t * 1e3, 4), "default_ms": round(default_ms, 4),
+           "tail_chunk": tc, "ms": round(t * 1e3, 4), "default_ms": round(default_ms, 4),
            "default": {k: default[k] for k in ("lane_entries", "grid_blocks", "chunk", "tail_entries",
                                                "tail_frames")},
-           "swept": len(main) + len(tail) - 1}
-    code.set_tuning(lane_entries=le, grid_blocks=gb, chunk=ch, tail_entries=te, tail_frames=tf, graphs=1)
+           "swept": len(main) + len(tail) + len(tcs) - 2}
+    code.set_tuning(lane_entries=le, grid_blocks=gb, chunk=ch, tail_entries=te, tail_frames=tf, tail_chunk=tc,
+                    graphs=1)
     if path:
         table = load_table(path)
         table[key(code, prec, F)] = ent

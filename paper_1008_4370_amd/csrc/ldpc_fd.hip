@@ -51,6 +51,8 @@ struct ldpc_fd_code_s {
   // chunks that start with at most tail_frames active frames use the variant
   // with 2^tail_logr entries per lane (shorter per-item latency)
   int tail_logr = 2, tail_frames = 128;
+  // passes per captured chunk once a chunk starts in the tail form (0: chunk)
+  int tail_chunk = 0;
   // 1: such chunks run the edge-parallel pass (k_fused_split)
   int split = 1;
   // variable-node form of the fused pass (tuning key PRECISE): 0 = FP32 prior
@@ -690,7 +692,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   const int chunk = c->chunk;
   std::lock_guard<std::mutex> lock(c->gmu);
   // The captured chunk for kernel variant lr (found in or added to the cache).
-  auto chunk_graph = [&](int lr, bool tail, int rgrid, hipGraphExec_t* exec) -> int32_t {
+  auto chunk_graph = [&](int lr, bool tail, int rgrid, int chunk, hipGraphExec_t* exec) -> int32_t {
     // zero-filled first: keys compare with memcmp, padding included
     ldpc_fd_code_s::GraphKey key;
     std::memset(&key, 0, sizeof key);
@@ -735,9 +737,11 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     return LDPC_FD_OK;
   };
   int left = F;
-  for (int p = 0; p < passes; p += chunk) {
+  for (int p = 0, ch = chunk; p < passes; p += ch) {
     hipGraphExec_t exec = nullptr;
-    if ((rc = chunk_graph(variant(left), is_tail(left), retire_grid(c, F, is_tail(left), left), &exec))) return rc;
+    const bool tail = is_tail(left);
+    ch = tail && c->tail_chunk > 0 ? c->tail_chunk : chunk;
+    if ((rc = chunk_graph(variant(left), tail, retire_grid(c, F, tail, left), ch, &exec))) return rc;
     HIP_TRY(hipGraphLaunch(exec, s));
     if (async) continue;   // passes after the last frame stops find no active frame
     if ((rc = read_count(w.nact, s, &left))) return rc;
@@ -1016,6 +1020,10 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
       if (value < 1 || value > (1 << 16)) return fail(LDPC_FD_E_INVALID, "quantisation step outside 1..65536");
       c->qstep = value;
       return LDPC_FD_OK;
+    case LDPC_FD_TUNE_TAIL_CHUNK:
+      if (value < 0 || value > 1000) return fail(LDPC_FD_E_INVALID, "tail chunk outside 0..1000");
+      c->tail_chunk = value;
+      return LDPC_FD_OK;
     default:
       return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
@@ -1035,6 +1043,7 @@ int32_t ldpc_fd_get_tuning(ldpc_fd_code c, int32_t key, int32_t* value) {
     case LDPC_FD_TUNE_TAIL_SPLIT: *value = c->split; return LDPC_FD_OK;
     case LDPC_FD_TUNE_QUANT_BITS: *value = c->qbits; return LDPC_FD_OK;
     case LDPC_FD_TUNE_QUANT_STEP: *value = c->qstep; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_TAIL_CHUNK: *value = c->tail_chunk; return LDPC_FD_OK;
     default: return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
 }

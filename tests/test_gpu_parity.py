@@ -286,6 +286,13 @@ def test_graph_replay_matches_eager_launches():
         eager = {k: v.cpu().numpy() for k, v in D.decode(gcode, L, 40, prec="fp32").items()}
         assert all(np.array_equal(eager[k], ref[k]) for k in ref)
         gcode.set_tuning(graphs=1)
+    # longer captured chunks for the tail passes (tuning key TAIL_CHUNK): the
+    # same results, passes after the last frame stops doing nothing
+    for tc in (1, 5, 32):
+        gcode.set_tuning(tail_chunk=tc, tail_frames=64)
+        out = {k: v.cpu().numpy() for k, v in D.decode(gcode, L, 40, prec="fp32").items()}
+        for k in ref:
+            assert np.array_equal(out[k], ref[k]), (tc, k)
     gcode.close()
 
 
