@@ -131,7 +131,10 @@ int32_t ldpc_fd_code_info(ldpc_fd_code code, int32_t *M, int32_t *N, int32_t *m,
                           int32_t *kmax);
 
 /* Bytes of caller-owned device workspace that ldpc_fd_decode needs for
- * `frames` frames at storage precision `prec` in decoder variant `mode`. */
+ * `frames` frames at storage precision `prec` in decoder variant `mode`.
+ * Errors: E_INVALID (unknown prec or mode), E_UNSUPPORTED (a storage type the
+ * mode does not have: PLAIN and FSP take FP32 only, LOGSP FP32 or LOG8,
+ * FUSED FP32, FP16 or BF16). */
 int32_t ldpc_fd_workspace_bytes(ldpc_fd_code code, int32_t frames, int32_t prec, int32_t mode,
                                 int64_t *bytes);
 
