@@ -128,6 +128,16 @@ def test_pool_sized_from_a_budget():
     for k, c in enumerate(codes):
         assert pool.slots[k] == (budget // 2) // D.pool_slot_bytes(c, "fp16")
     assert pool.slots == D.pool_budget_slots(codes, budget, "fp16")
+    # the query checks its arguments like the pool it sizes
+    with pytest.raises(D.LdpcFdError) as ei:
+        D.pool_budget_slots(codes, 1000, "fp32")
+    assert ei.value.rc == D.E_NOMEM
+    with pytest.raises(D.LdpcFdError) as ei:
+        D.pool_budget_slots(codes, 0, "fp16")
+    assert ei.value.rc == D.E_INVALID
+    with pytest.raises(D.LdpcFdError) as ei:
+        D.pool_budget_slots(codes, budget, "log8")
+    assert ei.value.rc == D.E_INVALID
     pool.close()
     with pytest.raises(D.LdpcFdError) as ei:
         D.Pool(codes, None, "fp32", hbm_budget=1000)
