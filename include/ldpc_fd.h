@@ -298,7 +298,8 @@ int32_t ldpc_fd_posterior(ldpc_fd_code code, int32_t frames, const float *llr, c
  * message buffer that holds that round's check-to-variable messages.
  * Errors: E_INVALID (NULL arguments with frames > 0, unknown prec, workspace
  *   smaller than the fused decode's), E_UNSUPPORTED (a code with column weights
- *   other than 2, or LDPC_FD_LOG8, neither of which a FUSED decode takes),
+ *   other than 2, or LDPC_FD_LOG8, neither of which a FUSED decode takes; a
+ *   workspace whose last decode retired in batches, tuning key BATCH_RETIRE),
  *   E_HIP. */
 int32_t ldpc_fd_decode_posterior(ldpc_fd_code code, int32_t frames, const float *llr, int32_t prec,
                                  const int32_t *iters, const void *workspace, int64_t workspace_bytes,
@@ -459,11 +460,22 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *     active count between graphs) for chunks that start with at most
  *     TAIL_FRAMES active frames; 0 (default) = CHUNK; 1..1000.  Results are
  *     identical for every value.
+ *   LDPC_FD_TUNE_BATCH_RETIRE: 1 = such a chunk of at most 32 edge-parallel
+ *     passes over at most 128 frames keeps every pass's decisions and checks
+ *     them all in one launch after the chunk (each frame still stops at its
+ *     first codeword round, with that round's hard, synd, iters and status);
+ *     0 (default) = syndromes and retirement after every pass.  The decode's
+ *     outputs are identical, but a frame that stopped inside a batched chunk
+ *     has its message state overwritten by the chunk's later passes, so
+ *     ldpc_fd_decode_posterior and ldpc_fd_decode_symbols return
+ *     E_UNSUPPORTED for a workspace whose last decode batched; a decode with
+ *     LDPC_FD_FLAG_VALIDATION never batches.
  * Errors: E_INVALID (unknown key or value), E_UNSUPPORTED (no such variant). */
 enum { LDPC_FD_TUNE_LANE_ENTRIES = 0, LDPC_FD_TUNE_GRID_BLOCKS = 1, LDPC_FD_TUNE_CHUNK = 2,
        LDPC_FD_TUNE_GRAPHS = 3, LDPC_FD_TUNE_TAIL_ENTRIES = 4, LDPC_FD_TUNE_TAIL_FRAMES = 5,
        LDPC_FD_TUNE_PRECISE = 6, LDPC_FD_TUNE_DECISION_MFMA = 7, LDPC_FD_TUNE_TAIL_SPLIT = 8,
-       LDPC_FD_TUNE_QUANT_BITS = 9, LDPC_FD_TUNE_QUANT_STEP = 10, LDPC_FD_TUNE_TAIL_CHUNK = 11 };
+       LDPC_FD_TUNE_QUANT_BITS = 9, LDPC_FD_TUNE_QUANT_STEP = 10, LDPC_FD_TUNE_TAIL_CHUNK = 11,
+       LDPC_FD_TUNE_BATCH_RETIRE = 12 };
 int32_t ldpc_fd_set_tuning(ldpc_fd_code code, int32_t key, int32_t value);
 int32_t ldpc_fd_get_tuning(ldpc_fd_code code, int32_t key, int32_t *value);
 

@@ -61,8 +61,15 @@ struct Impl {
     S* b0 = (S*)a.buf0;
     S* b1 = (S*)a.buf1;
 #define LFD_SPLIT(AR)                                                                                           \
-  hipLaunchKernelGGL((k_fused_split<G, KMAX, S, AR>), grid, block, lds_bytes, s, a.cd, a.prior, b0, b1, a.hard, \
-                     a.fsw, a.alist, a.nact, a.rnd, a.maxit, a.maxit_all)
+  do {                                                                                                         \
+    if (a.hist_hard)                                                                                           \
+      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, AR, true>), grid, block, lds_bytes, s, a.cd, a.prior, b0,   \
+                         b1, a.hard, a.fsw, a.alist, a.nact, a.rnd, a.maxit, a.maxit_all, a.roff, a.hist_hard,  \
+                         a.hist_fsw);                                                                          \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_fused_split<G, KMAX, S, AR, false>), grid, block, lds_bytes, s, a.cd, a.prior, b0,  \
+                         b1, a.hard, a.fsw, a.alist, a.nact, a.rnd, a.maxit, a.maxit_all, 0, nullptr, nullptr); \
+  } while (0)
     if constexpr (kPmfWords<S>) {
       LFD_SPLIT(kProbPrior);   // 16-bit storage: the default variable node only
     } else {

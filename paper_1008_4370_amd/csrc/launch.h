@@ -33,6 +33,11 @@ struct FusedArgs {
   bool mfma;            // decision transforms on the matrix cores
   int prec;             // storage type of the message buffers
   bool split;           // edge-parallel pass
+  // edge-parallel pass in a batched retirement (k_fused_split HIST): pass
+  // roff of the run, decisions to the rows hist_hard[slot][N], hist_fsw[slot][E]
+  int roff = 0;
+  uint8_t* hist_hard = nullptr;
+  uint8_t* hist_fsw = nullptr;
 };
 
 // PLAIN decoder kernels (k_var_plain / k_check_plain).

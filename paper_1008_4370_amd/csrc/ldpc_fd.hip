@@ -2,6 +2,7 @@
 // gfx950.  Entry points are declared and documented in include/ldpc_fd.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -53,6 +54,17 @@ struct ldpc_fd_code_s {
   int tail_logr = 2, tail_frames = 128;
   // passes per captured chunk once a chunk starts in the tail form (0: chunk)
   int tail_chunk = 0;
+  // 1: tail chunks of at most kHistRounds passes over at most kHistSlots
+  // frames retire once per chunk (k_tail_retire) instead of after every pass
+  int batch_retire = 0;
+  // workspaces whose last FUSED decode retired in batches: a frame that
+  // stopped inside a batched chunk has its messages overwritten by the
+  // chunk's later passes, so the decode-time posterior calls refuse them
+  std::vector<const void*> batched_ws;
+  bool workspace_batched(const void* ws) {
+    std::lock_guard<std::mutex> lock(gmu);
+    return std::find(batched_ws.begin(), batched_ws.end(), ws) != batched_ws.end();
+  }
   // 1: such chunks run the edge-parallel pass (k_fused_split)
   int split = 1;
   // variable-node form of the fused pass (tuning key PRECISE): 0 = FP32 prior
@@ -71,7 +83,7 @@ struct ldpc_fd_code_s {
   // Captured chunks of rounds of the fused decoder, keyed by everything their
   // kernel arguments depend on.
   struct GraphKey {
-    int F, prec, chunk, max_iter, logr, blocks, tail, rgrid, ar, early;
+    int F, prec, chunk, max_iter, logr, blocks, tail, rgrid, ar, early, batch;
     const void *ws, *llr, *hard, *synd, *iters, *status;
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
   };
@@ -171,7 +183,20 @@ struct FusedWs {
   uint32_t* mism;
   int* nact;       // nact[0]: active frames; nact[2]: syndrome/retire ticket
   int* rnd;  // [F] per-frame round
+  // batched retirement (k_tail_retire): decisions and sign words of a run's
+  // passes [kHistRounds][kHistSlots][N] / [..][E] and keep flags
+  // [kHistSlots]; NULL when the code's rows make them too large
+  uint8_t* hist_hard;
+  uint8_t* hist_fsw;
+  uint32_t* keepf;
 };
+
+// Bytes of the batched retirement's history buffers (0: not used for this
+// code, whose rows would take more than 64 MiB of them).
+size_t hist_bytes(const ldpc_fd_code_s* c) {
+  const size_t b = (size_t)kHistRounds * kHistSlots * ((size_t)c->N + c->E);
+  return b <= ((size_t)64 << 20) ? b : 0;
+}
 
 // esize: bytes per message entry (4; 1 for the LOGSP decoder's 8-bit codes).
 size_t plain_layout(const ldpc_fd_code_s* c, int F, char* base, PlainWs* w, int esize = 4) {
@@ -206,8 +231,13 @@ size_t fused_layout(const ldpc_fd_code_s* c, int F, int prec, char* base, FusedW
   char* p6 = take((size_t)F * 4);
   char* p7 = take(16);
   char* p8 = take((size_t)F * 4);
+  const bool hist = hist_bytes(c) > 0;
+  char* h1 = hist ? take((size_t)kHistRounds * kHistSlots * c->N) : nullptr;
+  char* h2 = hist ? take((size_t)kHistRounds * kHistSlots * c->E) : nullptr;
+  char* h3 = hist ? take(4 * (size_t)kHistSlots) : nullptr;
   if (w)
-    *w = FusedWs{(float*)pt, {b0, b1}, (uint8_t*)p2, (int*)p3, (int*)p4, (uint32_t*)p5, (uint32_t*)p6, (int*)p7, (int*)p8};
+    *w = FusedWs{(float*)pt, {b0, b1}, (uint8_t*)p2, (int*)p3, (int*)p4, (uint32_t*)p5, (uint32_t*)p6, (int*)p7, (int*)p8,
+                 (uint8_t*)h1, (uint8_t*)h2, (uint32_t*)h3};
   return off;
 }
 
@@ -629,6 +659,12 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     return LDPC_FD_OK;
   }
   if (mode != LDPC_FD_MODE_FUSED) return fail(LDPC_FD_E_INVALID, "unknown mode");
+  {
+    // until a batched chunk runs, this workspace will hold stopping-round messages
+    std::lock_guard<std::mutex> lock(c->gmu);
+    auto& v = c->batched_ws;
+    v.erase(std::remove(v.begin(), v.end(), (const void*)workspace), v.end());
+  }
   FusedWs w;
   fused_layout(c, F, prec, (char*)workspace, &w);
   hipLaunchKernelGGL(k_init_frames, dim3(fb), dim3(256), 0, s, F, (uint32_t*)nullptr, w.unsat, w.mism, w.alist,
@@ -654,6 +690,30 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     launch_syndrome_retire(c, F, hard, w.fsw, synd, w.unsat, w.mism, w.alist, w.nact, w.rnd, max_iter, nullptr, w.tmp,
                            iters, status, nullptr, nullptr, rgrid, st, early);
     return ok;
+  };
+  // Batched retirement: pass r of a run of edge-parallel passes writes its
+  // decisions to the history rows of run pass r; one k_tail_retire after the
+  // run checks every round and retires (one workgroup per active slot).
+  const int tgrid = std::max(1, std::min({F, std::max(c->tail_frames, 1), kHistSlots}));
+  const size_t tlds = 4 * (size_t)(((c->N + 3) >> 2) + ((c->E + 3) >> 2) + ((c->M + 3) >> 2));
+  auto enqueue_hist = [&](hipStream_t st, int lr, int r) {
+    FusedArgs fa{cd, tgrid, tp, w.buf[0], w.buf[1], hard, w.fsw, w.alist, w.nact, w.rnd, nullptr, max_iter,
+                 c->blocks, ar, c->mfma != 0, prec, true};
+    fa.roff = r;
+    fa.hist_hard = w.hist_hard + (size_t)r * kHistSlots * c->N;
+    fa.hist_fsw = w.hist_fsw + (size_t)r * kHistSlots * c->E;
+    return run_fused(c, lr, fa, st);
+  };
+  auto enqueue_tail_retire = [&](hipStream_t st, int R) {
+    hipLaunchKernelGGL(k_tail_retire, dim3((unsigned)tgrid), dim3(256), tlds, st, cd, R, w.hist_hard, w.hist_fsw, hard,
+                       synd, w.keepf, w.alist, w.nact, w.rnd, max_iter, (const int*)nullptr, early, w.tmp, iters,
+                       status, (int*)nullptr, (int*)nullptr, (unsigned*)(w.nact + 2));
+  };
+  // whether a chunk of ch passes that starts with `left` active frames retires once
+  const bool val = (flags & LDPC_FD_FLAG_VALIDATION) != 0;   // the posterior follows: keep the messages
+  auto batched = [&](bool tail, int left, int ch) {
+    return !val && tail && c->split && c->batch_retire && w.hist_hard && left <= kHistSlots && ch <= kHistRounds &&
+           tlds <= 60000;
   };
   // A frame needs at most max_iter + 1 passes (pass l forms round l's decision).
   const int passes = max_iter + 1;
@@ -692,7 +752,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   const int chunk = c->chunk;
   std::lock_guard<std::mutex> lock(c->gmu);
   // The captured chunk for kernel variant lr (found in or added to the cache).
-  auto chunk_graph = [&](int lr, bool tail, int rgrid, int chunk, hipGraphExec_t* exec) -> int32_t {
+  auto chunk_graph = [&](int lr, bool tail, int rgrid, int chunk, bool batch, hipGraphExec_t* exec) -> int32_t {
     // zero-filled first: keys compare with memcmp, padding included
     ldpc_fd_code_s::GraphKey key;
     std::memset(&key, 0, sizeof key);
@@ -706,6 +766,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     key.rgrid = rgrid;
     key.ar = ar;
     key.early = early;
+    key.batch = batch ? 1 : 0;
     key.ws = workspace;
     key.llr = tp;
     key.hard = hard;
@@ -723,7 +784,12 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     bool ok = true;
-    for (int r = 0; r < chunk; ++r) ok = enqueue_round(c->cap_stream, nullptr, nullptr, lr, tail, rgrid) && ok;
+    if (batch) {
+      for (int r = 0; r < chunk; ++r) ok = enqueue_hist(c->cap_stream, lr, r) && ok;
+      enqueue_tail_retire(c->cap_stream, chunk);
+    } else {
+      for (int r = 0; r < chunk; ++r) ok = enqueue_round(c->cap_stream, nullptr, nullptr, lr, tail, rgrid) && ok;
+    }
     HIP_TRY(hipStreamEndCapture(c->cap_stream, &graph));
     if (!ok) {
       (void)hipGraphDestroy(graph);
@@ -737,16 +803,34 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     return LDPC_FD_OK;
   };
   int left = F;
+  bool any_batch = false;
+  // record whether this workspace's messages are those of the stopping rounds
+  auto note_batch = [&]() {
+    auto& v = c->batched_ws;
+    if (any_batch && std::find(v.begin(), v.end(), (const void*)workspace) == v.end()) {
+      if (v.size() >= 64) v.erase(v.begin());
+      v.push_back(workspace);
+    }
+  };
   for (int p = 0, ch = chunk; p < passes; p += ch) {
     hipGraphExec_t exec = nullptr;
     const bool tail = is_tail(left);
     ch = tail && c->tail_chunk > 0 ? c->tail_chunk : chunk;
-    if ((rc = chunk_graph(variant(left), tail, retire_grid(c, F, tail, left), ch, &exec))) return rc;
+    const bool batch = batched(tail, left, ch);
+    any_batch = any_batch || batch;
+    if ((rc = chunk_graph(variant(left), tail, batch ? 0 : retire_grid(c, F, tail, left), ch, batch, &exec))) {
+      note_batch();
+      return rc;
+    }
     HIP_TRY(hipGraphLaunch(exec, s));
     if (async) continue;   // passes after the last frame stops find no active frame
-    if ((rc = read_count(w.nact, s, &left))) return rc;
+    if ((rc = read_count(w.nact, s, &left))) {
+      note_batch();
+      return rc;
+    }
     if (left == 0) break;
   }
+  note_batch();
   HIP_TRY(hipGetLastError());
   return LDPC_FD_OK;
 }
@@ -1024,6 +1108,10 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
       if (value < 0 || value > 1000) return fail(LDPC_FD_E_INVALID, "tail chunk outside 0..1000");
       c->tail_chunk = value;
       return LDPC_FD_OK;
+    case LDPC_FD_TUNE_BATCH_RETIRE:
+      if (value != 0 && value != 1) return fail(LDPC_FD_E_INVALID, "batch retire: 0 or 1");
+      c->batch_retire = value;
+      return LDPC_FD_OK;
     default:
       return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
@@ -1044,6 +1132,7 @@ int32_t ldpc_fd_get_tuning(ldpc_fd_code c, int32_t key, int32_t* value) {
     case LDPC_FD_TUNE_QUANT_BITS: *value = c->qbits; return LDPC_FD_OK;
     case LDPC_FD_TUNE_QUANT_STEP: *value = c->qstep; return LDPC_FD_OK;
     case LDPC_FD_TUNE_TAIL_CHUNK: *value = c->tail_chunk; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_BATCH_RETIRE: *value = c->batch_retire; return LDPC_FD_OK;
     default: return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
 }

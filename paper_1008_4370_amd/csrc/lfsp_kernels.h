@@ -810,14 +810,21 @@ __global__ __launch_bounds__(256, 2) void k_fused(DevCode cd, const float* __res
 // A check's latency is then one edge instead of k.  LDS: per wavefront T rows
 // of Q floats for the label permutations, and the stash [KMAX][T][Q], whose
 // first rows then hold the check's sums.
-template <class G, int KMAX, typename S, int AR>
+// HIST (batched retirement): the pass is pass roff of a run of passes between
+// two retirements, so a frame is at round rnd[f] + roff; frames past their
+// last round do nothing, and the decisions and sign words go to the rows of
+// the frame's slot in the active list, hist_hard[slot][N] and
+// hist_fsw[slot][E] (the run's pass roff), for the retirement to check.
+template <class G, int KMAX, typename S, int AR, bool HIST = false>
 __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const float* __restrict__ tp,
                                                            S* __restrict__ buf0, S* __restrict__ buf1,
                                                            uint8_t* __restrict__ hard, uint8_t* __restrict__ fsw,
                                                            const int* __restrict__ alist,
                                                            const int* __restrict__ nact_p,
                                                            const int* __restrict__ rnd,
-                                                           const int* __restrict__ maxit, int maxit_all) {
+                                                           const int* __restrict__ maxit, int maxit_all, int roff,
+                                                           uint8_t* __restrict__ hist_hard,
+                                                           uint8_t* __restrict__ hist_fsw) {
   extern __shared__ float lds[];
   float* stash = lds + KMAX * G::T * G::QP;
   const int j = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -832,9 +839,21 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
   for (long it = blockIdx.x; it < items; it += gridDim.x) {
     const int g = (int)(it / cd.M), c = (int)(it % cd.M);
     const int slot = g * G::T + fl;
-    const bool valid = slot < nact;
-    const int f = alist[valid ? slot : nact - 1];
-    const FrameState fs = frame_state(rnd, maxit, maxit_all, f);
+    const int f = alist[slot < nact ? slot : nact - 1];
+    FrameState fs = frame_state(rnd, maxit, maxit_all, f);
+    bool valid = slot < nact;
+    if constexpr (HIST) {
+      fs.ell += roff;
+      const int mi = maxit ? maxit[f] : maxit_all;
+      valid = valid && fs.ell <= mi;
+      fs.first = fs.ell == 0;
+      fs.decide = fs.ell >= 1;
+      fs.write = fs.ell < mi;
+    }
+    // rows of this frame's decisions and sign words (formed where they are
+    // written, so that no row pointer stays live across the item)
+    auto hrow = [&]() { return HIST ? hist_hard + (size_t)slot * cd.N : hard + (size_t)f * cd.N; };
+    auto frow = [&]() { return HIST ? hist_fsw + (size_t)slot * cd.E : fsw + (size_t)f * cd.E; };
     const int e0 = uni(cd.row_ptr[c]), deg = uni(cd.row_ptr[c + 1]) - e0;
     const size_t fb = (size_t)f * cd.E * G::Q;
     const S* cin = (fs.ell & 1) ? buf1 : buf0;
@@ -873,9 +892,9 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
           const int ho = uni(cd.e_label[eo]);
           decide_pmf_direct<G>(st, xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
           if (valid && fs.decide && zl == 0) {
-            hard[(size_t)f * cd.N + v] = (uint8_t)hd;
-            fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
-            fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
+            hrow()[v] = (uint8_t)hd;
+            frow()[e] = (uint8_t)fa;
+            frow()[eo] = (uint8_t)fo;
           }
         }
         symbol_prior_back<G, true>(st, zl);
@@ -896,9 +915,9 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
             const int ho = uni(cd.e_label[eo]);
             decide_pmf<G, true>(st, xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
             if (valid && fs.decide && zl == 0) {
-              hard[(size_t)f * cd.N + v] = (uint8_t)hd;
-              fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
-              fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
+              hrow()[v] = (uint8_t)hd;
+              frow()[e] = (uint8_t)fa;
+              frow()[eo] = (uint8_t)fo;
             }
           }
           symbol_prior_back<G>(st, zl);
@@ -914,9 +933,9 @@ __global__ __launch_bounds__(64 * KMAX) void k_fused_split(DevCode cd, const flo
         const int ho = uni(cd.e_label[eo]);
         decide<G>(st, xo, lds, rb, cf, zl, uni64(cd.colsT[h]), uni64(cd.colsT[ho]), hd, fa, fo);
         if (valid && fs.decide && zl == 0) {
-          hard[(size_t)f * cd.N + v] = (uint8_t)hd;
-          fsw[(size_t)f * cd.E + e] = (uint8_t)fa;
-          fsw[(size_t)f * cd.E + eo] = (uint8_t)fo;
+          hrow()[v] = (uint8_t)hd;
+          frow()[e] = (uint8_t)fa;
+          frow()[eo] = (uint8_t)fo;
         }
       }
       if constexpr (P)

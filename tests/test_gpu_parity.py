@@ -418,19 +418,59 @@ def test_edge_parallel_tail_pass_is_identical(case, precise):
     # 16-bit storage is built for the default variable node only
     precs = ("fp32", "fp16", "bf16") if precise == 2 else ("fp32",)
     res = {}
-    for split in (0, 1):
-        gcode.set_tuning(tail_split=split)
+    for split, batch in ((0, 1), (1, 0), (1, 1)):
+        gcode.set_tuning(tail_split=split, batch_retire=batch)
         for prec in precs:
             r = D.decode(gcode, L, 30, prec=prec, mode="fused")
-            res[split, prec] = {k2: v.cpu().numpy() for k2, v in r.items()}
+            res[(split, batch), prec] = {k2: v.cpu().numpy() for k2, v in r.items()}
     gcode.set_tuning(tail_frames=0)
     for prec in precs:
         r = D.decode(gcode, L, 30, prec=prec, mode="fused")
         res["none", prec] = {k2: v.cpu().numpy() for k2, v in r.items()}
     for prec in precs:
         for key in ("hard", "synd", "iters", "status"):
-            assert np.array_equal(res[0, prec][key], res[1, prec][key]), (prec, key)
-            assert np.array_equal(res["none", prec][key], res[1, prec][key]), (prec, key, "no tail")
+            assert np.array_equal(res[(0, 1), prec][key], res[(1, 0), prec][key]), (prec, key)
+            assert np.array_equal(res[(1, 0), prec][key], res[(1, 1), prec][key]), (prec, key, "batched")
+            assert np.array_equal(res["none", prec][key], res[(1, 1), prec][key]), (prec, key, "no tail")
+    gcode.close()
+
+
+@pytest.mark.parametrize("case", [CASES[5], CASES[8]], ids=lambda c: c[0])
+def test_batched_retirement_from_mid_decode(case):
+    """A batch larger than 128 frames retires after every pass until at most
+    128 frames are active, then keeps each tail chunk's decisions and retires
+    once per chunk (every frame still stops at its first codeword round):
+    decodes identical to retiring after every pass, for chunks shorter than,
+    equal to and unrelated to the frames' stopping rounds, with and without
+    early stopping."""
+    name, m, k, N, F, ebn0 = case
+    F = 300
+    print(f"[case] batched retirement {name} F={F}", flush=True)
+    code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0 - 0.5, seed=3)
+    gcode = D.Code.from_synth(code)
+    gcode.set_tuning(tail_frames=1 << 20, tail_entries=4, chunk=2)
+    L = _dev(llr)
+    gcode.set_tuning(batch_retire=0)
+    ref = {k2: v.cpu().numpy() for k2, v in D.decode(gcode, L, 40, prec="fp32", mode="fused").items()}
+    _check_outputs(ref, enc, 40)
+    assert len(np.unique(ref["iters"])) > 3
+    gcode.set_tuning(batch_retire=1)
+    for tch in (1, 3, 7, 32):
+        gcode.set_tuning(tail_chunk=tch)
+        out = {k2: v.cpu().numpy() for k2, v in D.decode(gcode, L, 40, prec="fp32", mode="fused").items()}
+        for key in ("hard", "synd", "iters", "status"):
+            assert np.array_equal(ref[key], out[key]), (tch, key)
+    dec = D.Decoder(gcode, F, "fp32", "fused")
+    for batch in (0, 1):
+        gcode.set_tuning(batch_retire=batch, tail_chunk=7)
+        r = dec.decode_ex(L[:100].contiguous(), 40, D.FLAG_NO_EARLY_STOP)   # at most 128 frames: batched
+        res = {k2: v.cpu().numpy() for k2, v in r.items()}
+        if batch == 0:
+            ref_ne = res
+        else:
+            for key in ("hard", "synd", "iters", "status"):
+                assert np.array_equal(ref_ne[key], res[key]), ("no early stop", key)
+    assert np.all(ref_ne["iters"] == 40)
     gcode.close()
 
 

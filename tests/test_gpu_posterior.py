@@ -165,3 +165,31 @@ def test_symbol_map_and_soft_output(case):
     assert sel.sum() > 0.9 * same.sum() * N
     assert np.array_equal(sym[sel], ref.symmap[sel])
     gcode.close()
+
+
+def test_posterior_after_batched_retirement_is_refused():
+    """With BATCH_RETIRE a frame that stops inside a batched tail chunk has its
+    messages overwritten by the chunk's later passes: the decode-time posterior
+    of such a workspace is refused (E_UNSUPPORTED), a VALIDATION decode does not
+    batch, and its posteriors equal those of a decode that never batched."""
+    name, m, k, N, F, ebn0 = CASES[5]
+    print(f"[case] batched posterior {name} F={F}", flush=True)
+    code, enc, cw, llr, tc = _setup(m, k, N, F, ebn0)
+    gcode = D.Code.from_synth(code)
+    gcode.set_tuning(tail_frames=1 << 20, tail_chunk=5)
+    L = _dev(llr)
+    dec = D.Decoder(gcode, F, "fp32", "fused")
+    dec(L, 20)
+    ref = dec.posterior().cpu().numpy()
+    gcode.set_tuning(batch_retire=1)
+    dec(L, 20)
+    with pytest.raises(D.LdpcFdError) as ei:
+        dec.posterior()
+    assert ei.value.rc == D.E_UNSUPPORTED
+    r = dec.decode_ex(L, 20, D.FLAG_VALIDATION)
+    assert np.array_equal(r["posterior"].cpu().numpy(), ref)
+    # a decode that does not batch makes the workspace readable again
+    gcode.set_tuning(batch_retire=0)
+    dec(L, 20)
+    assert np.array_equal(dec.posterior().cpu().numpy(), ref)
+    gcode.close()
