@@ -462,8 +462,11 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *     identical for every value.
  *   LDPC_FD_TUNE_BATCH_RETIRE: 1 = such a chunk of at most 32 edge-parallel
  *     passes over at most 128 frames keeps every pass's decisions and checks
- *     them all in one launch after the chunk (each frame still stops at its
- *     first codeword round, with that round's hard, synd, iters and status);
+ *     them all after the chunk (two launches: the syndromes of every pass and
+ *     frame in parallel, then the stopping rule and compaction; each frame
+ *     still stops at its first codeword round, with that round's hard, synd,
+ *     iters and status; the history buffers take 4096 (N + E + M + 4) bytes of
+ *     the workspace, none when that exceeds 64 MiB, and then nothing batches);
  *     0 (default) = syndromes and retirement after every pass.  The decode's
  *     outputs are identical, but a frame that stopped inside a batched chunk
  *     has its message state overwritten by the chunk's later passes, so

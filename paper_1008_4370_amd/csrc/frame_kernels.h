@@ -353,132 +353,157 @@ __global__ __launch_bounds__(256) void k_syndrome_retire(DevCode cd, const uint8
 
 // Batched retirement after a run of R passes of the edge-parallel pass in its
 // history form (k_fused_split HIST) over at most kHistSlots active frames, in
-// place of a syndrome and retirement launch after every pass.  One workgroup
-// per active slot (grid-stride): for r = 0, 1, ... the frame's decision of
-// round l = rnd[f] + r (rows hist_hard[r][slot], hist_fsw[r][slot]; none at
-// round 0) is checked as k_syndrome_retire checks it, and the first round that
-// stops the frame (both syndromes zero with early stopping, or its last
-// round) gives its outputs: hard and synd from that round, iters = l, status
-// with the mismatch bits of the rounds up to it and the converged bit.  A
-// frame that does not stop has iters set to its last round and rnd advanced by
-// R.  The rounds the run made after a frame's stopping round are ignored (they
-// only wrote state that nothing reads).  Every workgroup then counts itself
-// on the ticket (device-scope release of its keep flags), and the last one
-// compacts the active list in order (stopped frames appended to `done`).
-// *ticket is zero on entry and reset by the last workgroup.  LDS (dynamic):
-// N + E + M bytes, each rounded up to words.
+// place of a syndrome and retirement launch after every pass; two launches.
+// k_tail_syndromes, one workgroup per (run pass r, slot): the frame's
+// decision of round l = rnd[f] + r (rows hist_hard[r][slot],
+// hist_fsw[r][slot]; none at round 0 or past the frame's last round) is
+// checked as k_syndrome_retire checks it: direct syndrome row to
+// hist_synd[r][slot], flags hist_flag[r][slot] (bit 0 some check nonzero,
+// bit 1 the two syndromes differ).  k_tail_retire, one workgroup: the first
+// round that stops each frame (both syndromes zero with early stopping, or
+// its last round) gives its outputs (hard and synd from that round, iters = l,
+// status with the mismatch bits of the rounds up to it and the converged
+// bit); a frame that does not stop has iters set to its last round and rnd
+// advanced by R; the active list is compacted in order (stopped frames
+// appended to `done`).  The rounds the run made after a frame's stopping round
+// only overwrote its message state (which the decode-time posterior calls then
+// refuse to read).
 constexpr int kHistRounds = 32, kHistSlots = 128;
 
-__global__ __launch_bounds__(256) void k_tail_retire(DevCode cd, int R, const uint8_t* __restrict__ hist_hard,
-                                                     const uint8_t* __restrict__ hist_fsw,
-                                                     uint8_t* __restrict__ hard, uint8_t* __restrict__ synd,
-                                                     uint32_t* keepf, int* alist, int* nact_p, int* rnd,
-                                                     int maxit_all, const int* __restrict__ maxit, int early_stop,
-                                                     int* tmp, int32_t* iters, uint32_t* status, int* done,
-                                                     int* ndone, unsigned* ticket) {
-  extern __shared__ uint32_t smw[];
+__global__ __launch_bounds__(256) void k_tail_syndromes(DevCode cd, int S, const uint8_t* __restrict__ hist_hard,
+                                                        const uint8_t* __restrict__ hist_fsw,
+                                                        uint8_t* __restrict__ hist_synd, uint32_t* __restrict__ hist_flag,
+                                                        const int* __restrict__ alist, const int* __restrict__ nact_p,
+                                                        const int* __restrict__ rnd, int maxit_all,
+                                                        const int* __restrict__ maxit) {
+  extern __shared__ uint32_t smw[];   // [N] decisions, [E] sign words (bytes, word-rounded)
   __shared__ uint8_t s_exp[512];
   __shared__ uint16_t s_log[256];
   __shared__ int red[2];
-  __shared__ int wsum[4];
-  __shared__ int base_s;
-  __shared__ int last;
   const int tid = threadIdx.x;
+  const int r = blockIdx.x / S, slot = blockIdx.x % S;
   const int nact = *nact_p;
-  const int nw = (cd.N + 3) >> 2, ew = (cd.E + 3) >> 2;
+  if (slot >= nact) return;            // uniform over the block
+  const int f = alist[slot];
+  const int ell = rnd[f] + r;
+  const int mi = maxit ? maxit[f] : maxit_all;
+  if (ell < 1 || ell > mi) return;
+  const int nw = (cd.N + 3) >> 2;
   uint8_t* sh = reinterpret_cast<uint8_t*>(smw);
   uint8_t* sw = reinterpret_cast<uint8_t*>(smw + nw);
-  uint8_t* sy = reinterpret_cast<uint8_t*>(smw + nw + ew);
+  const uint8_t* hh = hist_hard + ((size_t)r * kHistSlots + slot) * cd.N;
+  const uint8_t* hf = hist_fsw + ((size_t)r * kHistSlots + slot) * cd.E;
   for (int i = tid; i < 512; i += blockDim.x) s_exp[i] = cd.gexp[i];
   for (int i = tid; i < 256; i += blockDim.x) s_log[i] = cd.glog[i];
-  for (int slot = blockIdx.x; slot < nact; slot += gridDim.x) {
+  for (int i = tid; i < cd.N; i += blockDim.x) sh[i] = hh[i];
+  for (int i = tid; i < cd.E; i += blockDim.x) sw[i] = hf[i];
+  if (tid == 0) {
+    red[0] = 0;
+    red[1] = 0;
+  }
+  __syncthreads();
+  uint8_t* sy = hist_synd + ((size_t)r * kHistSlots + slot) * cd.M;
+  int bad = 0, mm = 0;
+  for (int c = tid; c < cd.M; c += blockDim.x) {
+    const int e0 = cd.row_ptr[c], e1 = cd.row_ptr[c + 1];
+    int sd = 0, sf = 0;
+    for (int e = e0; e < e1; ++e) {
+      const uint32_t pk = cd.e_pack[e];
+      const int x = sh[pk & 0xFFFFFFu];
+      if (x) sd ^= s_exp[s_log[pk >> 24] + s_log[x]];
+      sf ^= sw[e];
+    }
+    sy[c] = (uint8_t)sd;
+    bad |= sd | sf;
+    mm |= sd != sf;
+  }
+  if (bad) atomicOr(&red[0], 1);
+  if (mm) atomicOr(&red[1], 1);
+  __syncthreads();
+  if (tid == 0) hist_flag[(size_t)r * kHistSlots + slot] = (red[0] ? 1u : 0u) | (red[1] ? 2u : 0u);
+}
+
+__global__ __launch_bounds__(256) void k_tail_retire(DevCode cd, int R, const uint8_t* __restrict__ hist_hard,
+                                                     const uint8_t* __restrict__ hist_synd,
+                                                     const uint32_t* __restrict__ hist_flag,
+                                                     uint8_t* __restrict__ hard, uint8_t* __restrict__ synd,
+                                                     int* alist, int* nact_p, int* rnd, int maxit_all,
+                                                     const int* __restrict__ maxit, int early_stop,
+                                                     int32_t* iters, uint32_t* status, int* done, int* ndone) {
+  __shared__ uint32_t s_flag[kHistRounds * kHistSlots];
+  __shared__ int stop_r[kHistSlots];   // stopping run pass of each slot, -1: continues
+  __shared__ int wsum[4];
+  const int tid = threadIdx.x;
+  const int nact = *nact_p;            // at most kHistSlots
+  // the run's flags to LDS, four independent loads in flight per thread
+  // (entries of rounds a frame did not check are read but never used)
+  const int nf = R * kHistSlots;
+  for (int i0 = 0; i0 < nf; i0 += 4 * 256) {
+    uint32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * 256 + tid;
+      v[u] = i < nf ? hist_flag[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * 256 + tid;
+      if (i < nf) s_flag[i] = v[u];
+    }
+  }
+  __syncthreads();
+  if (tid < nact) {
+    const int slot = tid;
     const int f = alist[slot];
     const int r0 = rnd[f];
     const int mi = maxit ? maxit[f] : maxit_all;
     uint32_t st = status[f];
-    int stop = 0, last_ell = 0;
-    for (int r = 0; r < R && !stop; ++r) {   // uniform over the block
+    int stop = -1, last_ell = 0;
+    for (int r = 0; r < R && stop < 0; ++r) {
       const int ell = r0 + r;
-      if (ell == 0) continue;                 // the frame's first pass: no decision
+      if (ell == 0) continue;           // the frame's first pass: no decision
       if (ell > mi) break;
-      const uint8_t* hh = hist_hard + ((size_t)r * kHistSlots + slot) * cd.N;
-      const uint8_t* hf = hist_fsw + ((size_t)r * kHistSlots + slot) * cd.E;
-      for (int i = tid; i < cd.N; i += blockDim.x) sh[i] = hh[i];
-      for (int i = tid; i < cd.E; i += blockDim.x) sw[i] = hf[i];
-      if (tid == 0) {
-        red[0] = 0;
-        red[1] = 0;
-      }
-      __syncthreads();
-      int bad = 0, mm = 0;
-      for (int c = tid; c < cd.M; c += blockDim.x) {
-        const int e0 = cd.row_ptr[c], e1 = cd.row_ptr[c + 1];
-        int sd = 0, sf = 0;
-        for (int e = e0; e < e1; ++e) {
-          const uint32_t pk = cd.e_pack[e];
-          const int x = sh[pk & 0xFFFFFFu];
-          if (x) sd ^= s_exp[s_log[pk >> 24] + s_log[x]];
-          sf ^= sw[e];
-        }
-        sy[c] = (uint8_t)sd;
-        bad |= sd | sf;
-        mm |= sd != sf;
-      }
-      if (bad) atomicOr(&red[0], 1);
-      if (mm) atomicOr(&red[1], 1);
-      __syncthreads();
-      const bool conv = red[0] == 0;
-      if (red[1]) st |= 2u;
+      const uint32_t fl = s_flag[r * kHistSlots + slot];
+      const bool conv = (fl & 1u) == 0;
+      if (fl & 2u) st |= 2u;
       last_ell = ell;
       if ((conv && early_stop) || ell >= mi) {
-        stop = 1;
+        stop = r;
         if (conv) st |= 1u;
-        for (int i = tid; i < cd.N; i += blockDim.x) hard[(size_t)f * cd.N + i] = sh[i];
-        for (int c = tid; c < cd.M; c += blockDim.x) synd[(size_t)f * cd.M + c] = sy[c];
       }
-      __syncthreads();   // the rows, syndromes and flags are rewritten by the next round
     }
-    if (tid == 0) {
-      if (last_ell >= 1) iters[f] = last_ell;
-      status[f] = st;
-      if (!stop) rnd[f] = r0 + R;
-      keepf[slot] = stop ? 0u : 1u;
-    }
-  }
-  if (tid == 0) {
-    if ((int)blockIdx.x < nact) __threadfence();
-    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    if (last_ell >= 1) iters[f] = last_ell;
+    status[f] = st;
+    if (stop < 0) rnd[f] = r0 + R;
+    stop_r[slot] = stop;
   }
   __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // stable compaction of the active list by the keep flags
+  // outputs of the stopped frames from their stopping round, one wave per slot
   const int lane = tid & 63, w = tid >> 6;
-  if (tid == 0) base_s = 0;
-  __syncthreads();
-  for (int start = 0; start < nact; start += 256) {
-    const int i = start + tid;
-    const int keep = i < nact ? (int)keepf[i] : 0;
-    const int f = i < nact ? alist[i] : -1;
-    if (done && i < nact && !keep) done[atomicAdd(ndone, 1)] = f;
-    const uint64_t b = __builtin_amdgcn_ballot_w64(keep);
-    const int pre = __builtin_popcountll(b & ((1ull << lane) - 1ull));
-    if (lane == 0) wsum[w] = __builtin_popcountll(b);
-    __syncthreads();
-    int off = base_s;
-    for (int k = 0; k < w; ++k) off += wsum[k];
-    if (keep) tmp[off + pre] = f;
-    __syncthreads();
-    if (tid == 0) base_s += wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    __syncthreads();
+  for (int slot = w; slot < nact; slot += 4) {
+    const int r = stop_r[slot];        // uniform over the wave
+    if (r < 0) continue;
+    const int f = alist[slot];
+    const uint8_t* hh = hist_hard + ((size_t)r * kHistSlots + slot) * cd.N;
+    const uint8_t* sy = hist_synd + ((size_t)r * kHistSlots + slot) * cd.M;
+#pragma unroll 4
+    for (int i = lane; i < cd.N; i += 64) hard[(size_t)f * cd.N + i] = hh[i];
+#pragma unroll 4
+    for (int c = lane; c < cd.M; c += 64) synd[(size_t)f * cd.M + c] = sy[c];
   }
-  const int total = base_s;
-  for (int i = tid; i < total; i += 256) alist[i] = tmp[i];
+  // stable compaction of the active list (one pass: nact <= 256)
+  const int keep = tid < nact ? (stop_r[tid] < 0 ? 1 : 0) : 0;
+  const int f = tid < nact ? alist[tid] : -1;
+  if (done && tid < nact && !keep) done[atomicAdd(ndone, 1)] = f;
+  const uint64_t b = __builtin_amdgcn_ballot_w64(keep);
+  const int pre = __builtin_popcountll(b & ((1ull << lane) - 1ull));
+  if (lane == 0) wsum[w] = __builtin_popcountll(b);
   __syncthreads();
-  if (tid == 0) {
-    *nact_p = total;
-    *ticket = 0u;
-  }
+  int off = 0;
+  for (int k = 0; k < w; ++k) off += wsum[k];
+  __syncthreads();                     // every thread has read alist[tid] before it is rewritten
+  if (keep) alist[off + pre] = f;
+  if (tid == 0) *nact_p = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 // Low-bit message storage, emulated in place on FP32 message arrays: every

@@ -183,18 +183,20 @@ struct FusedWs {
   uint32_t* mism;
   int* nact;       // nact[0]: active frames; nact[2]: syndrome/retire ticket
   int* rnd;  // [F] per-frame round
-  // batched retirement (k_tail_retire): decisions and sign words of a run's
-  // passes [kHistRounds][kHistSlots][N] / [..][E] and keep flags
-  // [kHistSlots]; NULL when the code's rows make them too large
+  // batched retirement (k_tail_syndromes, k_tail_retire): decisions, sign
+  // words and syndromes of a run's passes [kHistRounds][kHistSlots][N] /
+  // [..][E] / [..][M] and their check flags [kHistRounds][kHistSlots]; NULL
+  // when the code's rows make them too large
   uint8_t* hist_hard;
   uint8_t* hist_fsw;
-  uint32_t* keepf;
+  uint8_t* hist_synd;
+  uint32_t* hist_flag;
 };
 
 // Bytes of the batched retirement's history buffers (0: not used for this
 // code, whose rows would take more than 64 MiB of them).
 size_t hist_bytes(const ldpc_fd_code_s* c) {
-  const size_t b = (size_t)kHistRounds * kHistSlots * ((size_t)c->N + c->E);
+  const size_t b = (size_t)kHistRounds * kHistSlots * ((size_t)c->N + c->E + c->M + 4);
   return b <= ((size_t)64 << 20) ? b : 0;
 }
 
@@ -234,10 +236,11 @@ size_t fused_layout(const ldpc_fd_code_s* c, int F, int prec, char* base, FusedW
   const bool hist = hist_bytes(c) > 0;
   char* h1 = hist ? take((size_t)kHistRounds * kHistSlots * c->N) : nullptr;
   char* h2 = hist ? take((size_t)kHistRounds * kHistSlots * c->E) : nullptr;
-  char* h3 = hist ? take(4 * (size_t)kHistSlots) : nullptr;
+  char* h3 = hist ? take((size_t)kHistRounds * kHistSlots * c->M) : nullptr;
+  char* h4 = hist ? take(4 * (size_t)kHistRounds * kHistSlots) : nullptr;
   if (w)
     *w = FusedWs{(float*)pt, {b0, b1}, (uint8_t*)p2, (int*)p3, (int*)p4, (uint32_t*)p5, (uint32_t*)p6, (int*)p7, (int*)p8,
-                 (uint8_t*)h1, (uint8_t*)h2, (uint32_t*)h3};
+                 (uint8_t*)h1, (uint8_t*)h2, (uint8_t*)h3, (uint32_t*)h4};
   return off;
 }
 
@@ -692,10 +695,10 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     return ok;
   };
   // Batched retirement: pass r of a run of edge-parallel passes writes its
-  // decisions to the history rows of run pass r; one k_tail_retire after the
-  // run checks every round and retires (one workgroup per active slot).
+  // decisions to the history rows of run pass r; after the run,
+  // k_tail_syndromes checks every (pass, slot) and k_tail_retire retires.
   const int tgrid = std::max(1, std::min({F, std::max(c->tail_frames, 1), kHistSlots}));
-  const size_t tlds = 4 * (size_t)(((c->N + 3) >> 2) + ((c->E + 3) >> 2) + ((c->M + 3) >> 2));
+  const size_t tlds = 4 * (size_t)(((c->N + 3) >> 2) + ((c->E + 3) >> 2));
   auto enqueue_hist = [&](hipStream_t st, int lr, int r) {
     FusedArgs fa{cd, tgrid, tp, w.buf[0], w.buf[1], hard, w.fsw, w.alist, w.nact, w.rnd, nullptr, max_iter,
                  c->blocks, ar, c->mfma != 0, prec, true};
@@ -705,9 +708,11 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     return run_fused(c, lr, fa, st);
   };
   auto enqueue_tail_retire = [&](hipStream_t st, int R) {
-    hipLaunchKernelGGL(k_tail_retire, dim3((unsigned)tgrid), dim3(256), tlds, st, cd, R, w.hist_hard, w.hist_fsw, hard,
-                       synd, w.keepf, w.alist, w.nact, w.rnd, max_iter, (const int*)nullptr, early, w.tmp, iters,
-                       status, (int*)nullptr, (int*)nullptr, (unsigned*)(w.nact + 2));
+    hipLaunchKernelGGL(k_tail_syndromes, dim3((unsigned)(R * tgrid)), dim3(256), tlds, st, cd, tgrid, w.hist_hard,
+                       w.hist_fsw, w.hist_synd, w.hist_flag, w.alist, w.nact, w.rnd, max_iter, (const int*)nullptr);
+    hipLaunchKernelGGL(k_tail_retire, dim3(1), dim3(256), 0, st, cd, R, w.hist_hard, w.hist_synd, w.hist_flag, hard,
+                       synd, w.alist, w.nact, w.rnd, max_iter, (const int*)nullptr, early, iters, status,
+                       (int*)nullptr, (int*)nullptr);
   };
   // whether a chunk of ch passes that starts with `left` active frames retires once
   const bool val = (flags & LDPC_FD_FLAG_VALIDATION) != 0;   // the posterior follows: keep the messages
