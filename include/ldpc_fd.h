@@ -473,12 +473,20 @@ int32_t ldpc_fd_pool_active(ldpc_fd_pool pool, int32_t code, int32_t *n);
  *     ldpc_fd_decode_posterior and ldpc_fd_decode_symbols return
  *     E_UNSUPPORTED for a workspace whose last decode batched; a decode with
  *     LDPC_FD_FLAG_VALIDATION never batches.
+ *   LDPC_FD_TUNE_FIRST_CHUNK: FUSED passes before the first host read of the
+ *     active count (the first captured graph); 0 (default) = CHUNK; 1..1000.
+ *     With a long first chunk and a short CHUNK the decoder reads the count
+ *     often only once most frames have stopped, and reaches the tail form
+ *     sooner.  Results are identical for every value.
+ * The edge-parallel pass of a tail chunk covers 32 frames when the chunk
+ * starts with at most 32 active, 128 when with at most 128, else TAIL_FRAMES
+ * (and at most the batch).
  * Errors: E_INVALID (unknown key or value), E_UNSUPPORTED (no such variant). */
 enum { LDPC_FD_TUNE_LANE_ENTRIES = 0, LDPC_FD_TUNE_GRID_BLOCKS = 1, LDPC_FD_TUNE_CHUNK = 2,
        LDPC_FD_TUNE_GRAPHS = 3, LDPC_FD_TUNE_TAIL_ENTRIES = 4, LDPC_FD_TUNE_TAIL_FRAMES = 5,
        LDPC_FD_TUNE_PRECISE = 6, LDPC_FD_TUNE_DECISION_MFMA = 7, LDPC_FD_TUNE_TAIL_SPLIT = 8,
        LDPC_FD_TUNE_QUANT_BITS = 9, LDPC_FD_TUNE_QUANT_STEP = 10, LDPC_FD_TUNE_TAIL_CHUNK = 11,
-       LDPC_FD_TUNE_BATCH_RETIRE = 12 };
+       LDPC_FD_TUNE_BATCH_RETIRE = 12, LDPC_FD_TUNE_FIRST_CHUNK = 13 };
 int32_t ldpc_fd_set_tuning(ldpc_fd_code code, int32_t key, int32_t value);
 int32_t ldpc_fd_get_tuning(ldpc_fd_code code, int32_t key, int32_t *value);
 

@@ -61,7 +61,8 @@ def apply(code: D.Code, prec: str, frames: int, path: str = TABLE) -> dict | Non
                     graphs=1)
     if "tail_entries" in ent:
         code.set_tuning(tail_entries=ent["tail_entries"], tail_frames=ent["tail_frames"])
-    code.set_tuning(tail_chunk=ent.get("tail_chunk", 0), batch_retire=ent.get("batch_retire", 0))
+    code.set_tuning(tail_chunk=ent.get("tail_chunk", 0), batch_retire=ent.get("batch_retire", 0),
+                    first_chunk=ent.get("first_chunk", 0))
     return ent
 
 

@@ -54,6 +54,8 @@ struct ldpc_fd_code_s {
   int tail_logr = 2, tail_frames = 128;
   // passes per captured chunk once a chunk starts in the tail form (0: chunk)
   int tail_chunk = 0;
+  // passes in a decode's first captured chunk (0: chunk)
+  int first_chunk = 0;
   // 1: tail chunks of at most kHistRounds passes over at most kHistSlots
   // frames retire once per chunk (k_tail_retire) instead of after every pass
   int batch_retire = 0;
@@ -83,7 +85,7 @@ struct ldpc_fd_code_s {
   // Captured chunks of rounds of the fused decoder, keyed by everything their
   // kernel arguments depend on.
   struct GraphKey {
-    int F, prec, chunk, max_iter, logr, blocks, tail, rgrid, ar, early, batch;
+    int F, prec, chunk, max_iter, logr, blocks, tail, rgrid, sf, ar, early, batch;
     const void *ws, *llr, *hard, *synd, *iters, *status;
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
   };
@@ -314,9 +316,23 @@ constexpr int kRetireOneLaunchMax = 128;
 // Workgroups of the one-launch form for a code with F frame slots whose pass
 // starts with `left` active frames in the tail form, or 0 for the two-launch
 // form.
+// Frames the edge-parallel pass's grid covers for a chunk that starts with
+// `left` active frames (at most the tail threshold): 32 or 128 when the
+// count is within them, so that a high threshold does not size the grid of
+// the last passes, which run over a few frames.  The active count only falls
+// within a chunk, so the grid covers every active slot.
+int split_frames(const ldpc_fd_code_s* c, int F, int left) {
+  int cap = std::max(c->tail_frames, 1);
+  if (left <= 32)
+    cap = std::min(cap, 32);
+  else if (left <= 128)
+    cap = std::min(cap, 128);
+  return std::max(1, std::min(F, cap));
+}
+
 int retire_grid(const ldpc_fd_code_s* c, int F, bool tail, int left) {
   if (!tail || left > kRetireOneLaunchMax) return 0;
-  return std::max(1, std::min({F, std::max(c->tail_frames, 1), kRetireOneLaunchMax}));
+  return std::min(split_frames(c, F, left), kRetireOneLaunchMax);
 }
 
 // Syndromes of the active frames, stopping rule and compaction.  tail_grid > 0
@@ -682,11 +698,12 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   const int ar = prior ? kSymbolPrior : var_form(c->precise);
   // One pass over the active frames (each at its own round, see k_fused),
   // syndromes of the decisions it formed, stopping rule and compaction.
-  auto enqueue_round = [&](hipStream_t st, hipEvent_t e0, hipEvent_t e1, int lr, bool tail, int rgrid) {
+  // sf: frames the edge-parallel pass covers (split_frames), used in the tail
+  auto enqueue_round = [&](hipStream_t st, hipEvent_t e0, hipEvent_t e1, int lr, bool tail, int rgrid, int sf) {
     bool ok = true;
     if (e0) (void)hipEventRecord(e0, st);
     const bool split = tail && c->split;
-    const FusedArgs fa{cd, split ? std::min(F, std::max(c->tail_frames, 1)) : F, tp, w.buf[0], w.buf[1], hard,
+    const FusedArgs fa{cd, split ? sf : F, tp, w.buf[0], w.buf[1], hard,
                        w.fsw, w.alist, w.nact, w.rnd, nullptr, max_iter, c->blocks, ar, c->mfma != 0, prec, split};
     ok = run_fused(c, lr, fa, st);
     if (e1) (void)hipEventRecord(e1, st);
@@ -697,9 +714,9 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   // Batched retirement: pass r of a run of edge-parallel passes writes its
   // decisions to the history rows of run pass r; after the run,
   // k_tail_syndromes checks every (pass, slot) and k_tail_retire retires.
-  const int tgrid = std::max(1, std::min({F, std::max(c->tail_frames, 1), kHistSlots}));
+  // tgrid: slots the run covers (split_frames of its starting count, at most kHistSlots)
   const size_t tlds = 4 * (size_t)(((c->N + 3) >> 2) + ((c->E + 3) >> 2));
-  auto enqueue_hist = [&](hipStream_t st, int lr, int r) {
+  auto enqueue_hist = [&](hipStream_t st, int lr, int r, int tgrid) {
     FusedArgs fa{cd, tgrid, tp, w.buf[0], w.buf[1], hard, w.fsw, w.alist, w.nact, w.rnd, nullptr, max_iter,
                  c->blocks, ar, c->mfma != 0, prec, true};
     fa.roff = r;
@@ -707,7 +724,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     fa.hist_fsw = w.hist_fsw + (size_t)r * kHistSlots * c->E;
     return run_fused(c, lr, fa, st);
   };
-  auto enqueue_tail_retire = [&](hipStream_t st, int R) {
+  auto enqueue_tail_retire = [&](hipStream_t st, int R, int tgrid) {
     hipLaunchKernelGGL(k_tail_syndromes, dim3((unsigned)(R * tgrid)), dim3(256), tlds, st, cd, tgrid, w.hist_hard,
                        w.hist_fsw, w.hist_synd, w.hist_flag, w.alist, w.nact, w.rnd, max_iter, (const int*)nullptr);
     hipLaunchKernelGGL(k_tail_retire, dim3(1), dim3(256), 0, st, cd, R, w.hist_hard, w.hist_synd, w.hist_flag, hard,
@@ -728,25 +745,31 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   // (asynchronous decodes never learn the active count: full variant throughout)
   auto is_tail = [&](int left) { return !async && left <= c->tail_frames; };
   auto variant = [&](int left) { return is_tail(left) ? c->tail_logr : c->logr; };
+  // passes in the first chunk (host read of the active count after them)
+  const int first = c->first_chunk > 0 ? c->first_chunk : c->chunk;
   if (!c->graphs || t_prof.on) {
     int lr = variant(F);
     bool tail = is_tail(F);
     int rgrid = retire_grid(c, F, tail, F);
-    for (int p = 1; p <= passes; ++p) {
+    int sf = split_frames(c, F, F);
+    for (int p = 1, next = first; p <= passes; ++p) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (t_prof.on) {
         e0 = t_prof.get();
         e1 = t_prof.get();
         if (e0 && e1) t_prof.ev[LDPC_FD_K_FUSED].emplace_back(e0, e1);
       }
-      if (!enqueue_round(s, e0, e1, lr, tail, rgrid)) return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
-      if (!async && (p % c->chunk == 0 || p == passes)) {
+      if (!enqueue_round(s, e0, e1, lr, tail, rgrid, sf))
+        return fail(LDPC_FD_E_UNSUPPORTED, "no kernel for this code");
+      if (!async && (p == next || p == passes)) {
         int left = 0;
         if ((rc = read_count(w.nact, s, &left))) return rc;
         if (left == 0) break;
         lr = variant(left);
         tail = is_tail(left);
         rgrid = retire_grid(c, F, tail, left);
+        sf = split_frames(c, F, left);
+        next = p + c->chunk;
       }
     }
     HIP_TRY(hipGetLastError());
@@ -757,7 +780,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   const int chunk = c->chunk;
   std::lock_guard<std::mutex> lock(c->gmu);
   // The captured chunk for kernel variant lr (found in or added to the cache).
-  auto chunk_graph = [&](int lr, bool tail, int rgrid, int chunk, bool batch, hipGraphExec_t* exec) -> int32_t {
+  auto chunk_graph = [&](int lr, bool tail, int rgrid, int sf, int chunk, bool batch, hipGraphExec_t* exec) -> int32_t {
     // zero-filled first: keys compare with memcmp, padding included
     ldpc_fd_code_s::GraphKey key;
     std::memset(&key, 0, sizeof key);
@@ -769,6 +792,7 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     key.blocks = c->blocks;
     key.tail = tail ? 1 : 0;
     key.rgrid = rgrid;
+    key.sf = tail ? sf : 0;
     key.ar = ar;
     key.early = early;
     key.batch = batch ? 1 : 0;
@@ -790,10 +814,12 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     bool ok = true;
     if (batch) {
-      for (int r = 0; r < chunk; ++r) ok = enqueue_hist(c->cap_stream, lr, r) && ok;
-      enqueue_tail_retire(c->cap_stream, chunk);
+      const int tgrid = std::min(sf, kHistSlots);
+      for (int r = 0; r < chunk; ++r) ok = enqueue_hist(c->cap_stream, lr, r, tgrid) && ok;
+      enqueue_tail_retire(c->cap_stream, chunk, tgrid);
     } else {
-      for (int r = 0; r < chunk; ++r) ok = enqueue_round(c->cap_stream, nullptr, nullptr, lr, tail, rgrid) && ok;
+      for (int r = 0; r < chunk; ++r)
+        ok = enqueue_round(c->cap_stream, nullptr, nullptr, lr, tail, rgrid, sf) && ok;
     }
     HIP_TRY(hipStreamEndCapture(c->cap_stream, &graph));
     if (!ok) {
@@ -820,10 +846,11 @@ int32_t decode_impl(ldpc_fd_code c, int32_t F, const float* llr, const float* pr
   for (int p = 0, ch = chunk; p < passes; p += ch) {
     hipGraphExec_t exec = nullptr;
     const bool tail = is_tail(left);
-    ch = tail && c->tail_chunk > 0 ? c->tail_chunk : chunk;
+    ch = tail && c->tail_chunk > 0 ? c->tail_chunk : p == 0 ? first : chunk;
     const bool batch = batched(tail, left, ch);
     any_batch = any_batch || batch;
-    if ((rc = chunk_graph(variant(left), tail, batch ? 0 : retire_grid(c, F, tail, left), ch, batch, &exec))) {
+    const int sf = split_frames(c, F, left);
+    if ((rc = chunk_graph(variant(left), tail, batch ? 0 : retire_grid(c, F, tail, left), sf, ch, batch, &exec))) {
       note_batch();
       return rc;
     }
@@ -1117,6 +1144,10 @@ int32_t ldpc_fd_set_tuning(ldpc_fd_code c, int32_t key, int32_t value) {
       if (value != 0 && value != 1) return fail(LDPC_FD_E_INVALID, "batch retire: 0 or 1");
       c->batch_retire = value;
       return LDPC_FD_OK;
+    case LDPC_FD_TUNE_FIRST_CHUNK:
+      if (value < 0 || value > 1000) return fail(LDPC_FD_E_INVALID, "first chunk outside 0..1000");
+      c->first_chunk = value;
+      return LDPC_FD_OK;
     default:
       return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
@@ -1138,6 +1169,7 @@ int32_t ldpc_fd_get_tuning(ldpc_fd_code c, int32_t key, int32_t* value) {
     case LDPC_FD_TUNE_QUANT_STEP: *value = c->qstep; return LDPC_FD_OK;
     case LDPC_FD_TUNE_TAIL_CHUNK: *value = c->tail_chunk; return LDPC_FD_OK;
     case LDPC_FD_TUNE_BATCH_RETIRE: *value = c->batch_retire; return LDPC_FD_OK;
+    case LDPC_FD_TUNE_FIRST_CHUNK: *value = c->first_chunk; return LDPC_FD_OK;
     default: return fail(LDPC_FD_E_INVALID, "unknown tuning key");
   }
 }

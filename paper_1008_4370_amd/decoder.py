@@ -22,7 +22,7 @@ MODE = {"plain": 0, "fused": 1, "logsp": 2, "fsp": 3}
 STATUS_CONVERGED, STATUS_MISMATCH = 1, 2
 K_FUSED, K_CHECK, K_VAR = 0, 1, 2
 TUNE = {"lane_entries": 0, "grid_blocks": 1, "chunk": 2, "graphs": 3, "tail_entries": 4, "tail_frames": 5, "precise": 6, "decision_mfma": 7, "tail_split": 8,
-        "quant_bits": 9, "quant_step": 10, "tail_chunk": 11, "batch_retire": 12}
+        "quant_bits": 9, "quant_step": 10, "tail_chunk": 11, "batch_retire": 12, "first_chunk": 13}
 
 _lib = None
 _c_void_p, _i32, _i64, _u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32

@@ -293,6 +293,16 @@ def test_graph_replay_matches_eager_launches():
         out = {k: v.cpu().numpy() for k, v in D.decode(gcode, L, 40, prec="fp32").items()}
         for k in ref:
             assert np.array_equal(out[k], ref[k]), (tc, k)
+    # a first chunk of its own length (tuning key FIRST_CHUNK) with short later
+    # chunks and a tail threshold above 128, so that tail chunks start with
+    # more than 128, at most 128 and at most 32 active frames (the
+    # edge-parallel grid sized by that count), with and without batched
+    # retirement, replayed and launched eagerly
+    for fc, ch, br, g in ((3, 1, 0, 1), (6, 2, 1, 1), (5, 2, 1, 0), (9, 3, 1, 1)):
+        gcode.set_tuning(first_chunk=fc, chunk=ch, tail_frames=200, tail_chunk=0, batch_retire=br, graphs=g)
+        out = {k: v.cpu().numpy() for k, v in D.decode(gcode, L, 40, prec="fp32").items()}
+        for k in ref:
+            assert np.array_equal(out[k], ref[k]), (fc, ch, br, g, k)
     gcode.close()
 
 
