@@ -1,6 +1,7 @@
 """The decode entry point with an argument struct and flags (early stop off,
 validation posteriors, asynchronous enqueueing), several rounds from an
-imported state, and a pool sized from an HBM budget, through the C-ABI."""
+imported state, a pool sized from an HBM budget and the chunk tuning keys,
+through the C-ABI."""
 import numpy as np
 import pytest
 
@@ -144,3 +145,24 @@ def test_pool_sized_from_a_budget():
     assert ei.value.rc == D.E_NOMEM
     for c in codes:
         c.close()
+
+
+def test_chunk_tuning_keys_round_trip_and_reject_out_of_range_values():
+    """FIRST_CHUNK, TAIL_CHUNK and BATCH_RETIRE read back what was set (0 is
+    each one's default) and refuse values outside their ranges with
+    E_INVALID, leaving the setting unchanged."""
+    name, m, k, N, F, ebn0 = CASES[0]
+    code, enc, cw, llr, tc = _setup(m, k, N, 4, ebn0)
+    gcode = D.Code.from_synth(code)
+    t = gcode.get_tuning()
+    assert (t["first_chunk"], t["tail_chunk"], t["batch_retire"]) == (0, 0, 0)
+    gcode.set_tuning(first_chunk=9, tail_chunk=17, batch_retire=1)
+    t = gcode.get_tuning()
+    assert (t["first_chunk"], t["tail_chunk"], t["batch_retire"]) == (9, 17, 1)
+    for key, bad in (("first_chunk", -1), ("first_chunk", 1001), ("tail_chunk", 1001), ("batch_retire", 2)):
+        with pytest.raises(D.LdpcFdError) as ei:
+            gcode.set_tuning(**{key: bad})
+        assert ei.value.rc == D.E_INVALID, key
+    t = gcode.get_tuning()
+    assert (t["first_chunk"], t["tail_chunk"], t["batch_retire"]) == (9, 17, 1)
+    gcode.close()
