@@ -81,11 +81,13 @@ def _time_decode(dec, llr, max_iter, reps):
 
 def tune(code: D.Code, llr, prec: str = "fp32", max_iter: int = 100, reps: int = 3,
          grid_blocks=(2048, 4096, 8192, 16384, 32768), chunks=(4, 8), tail_frames=(0, 32, 128, 512, 2048, 1 << 20),
-         tail_chunks=(0, 16, 32), path: str | None = TABLE, log=None) -> dict:
+         tail_chunks=(0, 16, 32), later_chunks=(2, 3), path: str | None = TABLE, log=None) -> dict:
     """Sweep the launch choices for decoding `llr` (device [F][N][m]) and record
     the best: first the main variant, grid and chunk (tail variant at its
     defaults), then the tail variant and its threshold, then the number of
-    passes per captured graph in the tail."""
+    passes per captured graph in the tail, then batched retirement of the tail
+    (with the tail chunk chosen again), then shorter chunks after a first chunk
+    of the chosen length."""
     m, kmax, N = code.m, code.kmax, code.N
     F = int(llr.shape[0])
     dec = D.Decoder(code, F, prec, "fused")
@@ -93,7 +95,7 @@ def tune(code: D.Code, llr, prec: str = "fp32", max_iter: int = 100, reps: int =
     default_ms = _time_decode(dec, llr, max_iter, reps) * 1e3
 
     def run(**kw):
-        code.set_tuning(graphs=1, **kw)
+        code.set_tuning(graphs=1, **{"tail_chunk": 0, "batch_retire": 0, "first_chunk": 0, **kw})
         t = _time_decode(dec, llr, max_iter, reps)
         if log:
             log(f"[autotune] m={m} k={kmax} N={N} {prec} F={F}: {kw}: {t * 1e3:.3f} ms")
@@ -108,19 +110,29 @@ def tune(code: D.Code, llr, prec: str = "fp32", max_iter: int = 100, reps: int =
     for te, tf in itertools.product(lane_choices(m, kmax), tail_frames):
         tail.append((run(lane_entries=le, grid_blocks=gb, chunk=ch, tail_entries=te, tail_frames=tf), te, tf))
     t, te, tf = min(tail)
+    base = dict(lane_entries=le, grid_blocks=gb, chunk=ch, tail_entries=te, tail_frames=tf)
     tcs = [(t, 0)]
     for tc in tail_chunks:
         if tc:
-            tcs.append((run(lane_entries=le, grid_blocks=gb, chunk=ch, tail_entries=te, tail_frames=tf,
-                            tail_chunk=tc), tc))
+            tcs.append((run(**base, tail_chunk=tc), tc))
     t, tc = min(tcs)
-    ent = {"lane_entries": le, "grid_blocks": gb, "chunk": ch, "tail_entries": te, "tail_frames": tf,
-           "tail_chunk": tc, "ms": round(t * 1e3, 4), "default_ms": round(default_ms, 4),
+    brs = [(t, 0, tc)]
+    for tcb in tail_chunks:
+        brs.append((run(**base, tail_chunk=tcb, batch_retire=1), 1, tcb))
+    t, br, tc = min(brs)
+    fcs = [(t, 0, ch)]
+    for later in later_chunks:
+        if later < ch:
+            fcs.append((run(**{**base, "chunk": later}, tail_chunk=tc, batch_retire=br, first_chunk=ch), ch, later))
+    t, fc, ch_after = min(fcs)
+    ent = {"lane_entries": le, "grid_blocks": gb, "chunk": ch_after, "first_chunk": fc, "tail_entries": te,
+           "tail_frames": tf, "tail_chunk": tc, "batch_retire": br, "ms": round(t * 1e3, 4),
+           "default_ms": round(default_ms, 4),
            "default": {k: default[k] for k in ("lane_entries", "grid_blocks", "chunk", "tail_entries",
                                                "tail_frames")},
-           "swept": len(main) + len(tail) + len(tcs) - 2}
-    code.set_tuning(lane_entries=le, grid_blocks=gb, chunk=ch, tail_entries=te, tail_frames=tf, tail_chunk=tc,
-                    graphs=1)
+           "swept": len(main) + len(tail) + len(tcs) + len(brs) + len(fcs) - 4}
+    code.set_tuning(lane_entries=le, grid_blocks=gb, chunk=ch_after, first_chunk=fc, tail_entries=te,
+                    tail_frames=tf, tail_chunk=tc, batch_retire=br, graphs=1)
     if path:
         table = load_table(path)
         table[key(code, prec, F)] = ent
